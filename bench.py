@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Throughput of one enormous in-memory 1D complex FFT on one MI355X.
+
+Workload (default): forward in-place transform of N = 2^30 complex128 points
+(16 GiB), inputs i.i.d. uniform [-1, 1) per component from a seed, already
+resident in HBM.  A step is one whole transform (every pass of the plan).
+Reports GFLOP/s = 5 N log2 N / t (the nominal complex-FFT count; the paper's
+Eq. "eqflops" is the real-input half of it), per-pass HBM bandwidth from HIP
+events recorded on the launch stream inside the timed region, the same
+transform in complex64 for the FP32 speedup and its error against the FP64
+path, a device-copy ceiling, and the FP64 CPU oracle timed on a bounded
+sample on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--log2n Q] [--no-fp32] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+METRIC = "1D C2C FFT GFLOP/s (5N·log2N/t) + HBM GB/s % peak, FP64 vs FP32"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("efft_kernels.hip", "efft_device.hpp", "efft_internal.hpp", "efft_api.hip"):
+        with open(os.path.join(ROOT, "paper_1409_5757_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(workload_key: str, pass_index: int):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    entry = rec.get(workload_key, {})
+    if entry.get("source_hash") != kernel_source_hash():
+        return None
+    p = entry.get("passes", {}).get(str(pass_index))
+    return None if p is None else p.get("hbm_bytes")
+
+
+def time_transform(plan, x, steps: int, warmup: int):
+    """Warm up, then time exactly `steps` transforms; per-pass event times."""
+    import torch
+    for _ in range(warmup):
+        plan.execute(x)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(plan.passes + 1)] for _ in range(steps)]
+    for row in evs:  # materialise every hipEvent before the timed region
+        for e in row:
+            e.record()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for row in evs:
+        plan.execute_events(x, x, [e.cuda_event for e in row])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_pass = [sum(row[i].elapsed_time(row[i + 1]) for row in evs) / steps for i in range(plan.passes)]
+    event_step = sum(row[0].elapsed_time(row[-1]) for row in evs) / steps
+    return wall / steps * 1e3, event_step, per_pass
+
+
+def copy_ceiling(nbytes: int) -> float:
+    """Device-to-device copy bandwidth (read + write) in GB/s."""
+    import torch
+    n = nbytes // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(budget_s: float = 12.0):
+    """The FP64 oracle (radix-2, OpenMP) on 2^24-point transforms, repeated
+    until the budget is used; GFLOP/s by the same 5 N log2 N count."""
+    import numpy as np
+    import oracle
+    from paper_1409_5757_amd import inputs
+    q = 24
+    n = 1 << q
+    x = inputs.generate("uniform", 0, n)
+    lib = oracle.load()
+    reps, t_total = 0, 0.0
+    while t_total < budget_s and reps < 50:
+        t0 = time.perf_counter()
+        oracle.fft(x, -1, lib=lib)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    per = t_total / reps
+    return {"value": round(5 * n * q / per / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.threads(lib),
+            "kind": "oracle",
+            "sample": f"{reps} forward transforms of N=2^{q} complex128 (uniform [-1,1)), "
+                      f"{per:.2f} s each; same 5N log2N count"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=30)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one transform on one GPU; runs on more than one GPU are not "
+              "part of this benchmark (use --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1409_5757_amd import _lib, api, inputs
+
+    _lib.load()  # fails loudly if the library is missing
+    q = args.log2n
+    n = 1 << q
+    dev = torch.device("cuda", 0)
+    x = torch.empty(n, dtype=torch.complex128, device=dev)
+    inputs.fill_uniform_torch(x, seed=0)
+    plan = api.Plan(n, torch.complex128, -1, True, device=dev)
+    digits, passes = _lib.schedule(n, 2, True)
+    ms_step, ms_events, per_pass = time_transform(plan, x, args.steps, args.warmup)
+    gflops = 5 * n * q / (ms_step * 1e-3) / 1e9
+    bytes_pass = 2 * n * 16
+    dom = max(range(len(per_pass)), key=lambda i: per_pass[i])
+    achieved = bytes_pass / (per_pass[dom] * 1e-3) / 1e9
+    workload_key = f"c128_inplace_fwd_q{q}"
+    traffic = traffic_record(workload_key, dom)
+    passes_out = [{"pass": i, "ms": round(t, 4), "GBps": round(bytes_pass / (t * 1e-3) / 1e9, 1)}
+                  for i, t in enumerate(per_pass)]
+
+    result = {
+        "metric": METRIC,
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"forward in-place 1D C2C FFT, N=2^{q} complex128 "
+                               f"({n * 16 / 2**30:.0f} GiB), uniform [-1,1) inputs in HBM",
+                   "log2n": q, "inplace": True, "digits_log2": digits, "passes": passes},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": traffic, "kernel_pass": dom},
+        "hbm_GBps_whole_transform": round(passes * bytes_pass / (ms_events * 1e-3) / 1e9, 1),
+        "passes_detail": passes_out,
+    }
+    del x
+    torch.cuda.empty_cache()
+
+    if not args.no_fp32:
+        x32 = torch.empty(n, dtype=torch.complex64, device=dev)
+        inputs.fill_uniform_torch(x32, seed=0)
+        p32 = api.Plan(n, torch.complex64, -1, True, device=dev)
+        ms32, ev32, pp32 = time_transform(p32, x32, args.steps, args.warmup)
+        # error of the FP32 path against the FP64 path on the same input
+        inputs.fill_uniform_torch(x32, seed=1)
+        x64 = x32.to(torch.complex128)
+        p32.execute(x32)
+        plan.execute(x64)
+        torch.cuda.synchronize()
+        diff = (x32.to(torch.complex128) - x64)
+        rel = (torch.linalg.vector_norm(diff) / torch.linalg.vector_norm(x64)).item()
+        mabs = diff.abs().max().item()
+        del diff, x64
+        result["fp32"] = {
+            "workload": f"forward in-place N=2^{q} complex64", "value": round(5 * n * q / (ms32 * 1e-3) / 1e9, 2),
+            "unit": "GFLOP/s", "ms_per_step": round(ms32, 4), "speedup_vs_fp64": round(ms_step / ms32, 3),
+            "rel_l2_vs_fp64_path": rel, "max_abs_vs_fp64_path": mabs,
+            "passes_detail": [{"pass": i, "ms": round(t, 4), "GBps": round(2 * n * 8 / (t * 1e-3) / 1e9, 1)}
+                              for i, t in enumerate(pp32)]}
+        del x32
+        torch.cuda.empty_cache()
+
+    result["copy_ceiling_GBps"] = round(copy_ceiling(min(8 << 30, n * 16)), 1)
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

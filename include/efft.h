@@ -1,0 +1,158 @@
+/*
+ * efft.h -- C ABI of an MI355X (gfx950) library for one very large in-memory
+ * one-dimensional complex-to-complex FFT, N = 2^q points.
+ *
+ * Operation (Asai & Vladimirov, "EFFT", Section 1, Eq. "eqf"):
+ *
+ *     F_k = sum_{n=0}^{N-1} x_n * exp(sign * 2*pi*i * k*n / N),   0 <= k < N,
+ *
+ * with sign = -1 (EFFT_FORWARD, the paper's transform as written) or
+ * sign = +1 (EFFT_BACKWARD, the conjugate-sign transform; the paper defines
+ * only the forward one).  Neither direction is scaled: backward(forward(x))
+ * equals N*x, and the backward transform is the exact adjoint of the forward
+ * one.  Input and output are in natural order (F_k at index k).
+ *
+ * The plan/execute split follows the paper's usage flow of a transform
+ * handle that is created once, committed, and then reused (Section 2.1,
+ * Listing "code:dfti"; Section 3.1, the handles built once at initialisation
+ * because creating them costs more than a transform).  Like the paper's
+ * EFFT_Transform (Section 4, Listing "code:efftheader"), the transform size is
+ * the only required parameter; the decomposition (the paper's number of
+ * splits) is chosen internally.
+ *
+ * Data layout: interleaved complex (re, im), the layout of torch.complex64 /
+ * torch.complex128 and of the paper's stride-2 complex arrays (Section 3.4):
+ *   EFFT_C64  -- float  re, im (8 bytes per element), FP32 storage and
+ *                arithmetic; every twiddle factor is generated in FP64 and
+ *                rounded once to FP32.
+ *   EFFT_C128 -- double re, im (16 bytes per element), FP64 throughout.
+ *
+ * Memory: every data pointer is a device pointer in the calling process's
+ * current HIP device, owned by the caller, and must be aligned to one element
+ * (8 bytes for EFFT_C64, 16 for EFFT_C128).  A plan owns only its FP64
+ * twiddle tables (a few MiB at most), allocated on the device that is current
+ * when the plan is created; efft_destroy frees them.
+ *
+ * Asynchrony and threads: efft_exec / efft_exec_oop only enqueue kernels on
+ * the given stream (a hipStream_t; NULL selects the default stream) and
+ * return; device-side faults surface at the caller's next synchronisation.
+ * A plan is immutable after creation and may be executed concurrently from
+ * several streams, since it holds no scratch memory.  Error statuses from
+ * efft_plan are kept per host thread (efft_last_error).
+ *
+ * Errors: every function that returns int returns EFFT_OK (0) or one of the
+ * negative EFFT_ERR_* codes below; efft_strerror names them.
+ */
+#ifndef EFFT_H
+#define EFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct efft_plan_s efft_plan_t; /* opaque */
+
+/* element types (interleaved complex) */
+enum { EFFT_C64 = 1, EFFT_C128 = 2 };
+
+/* direction = sign of the exponent in Eq. "eqf" */
+enum { EFFT_FORWARD = -1, EFFT_BACKWARD = 1 };
+
+/* status codes */
+enum {
+    EFFT_OK = 0,
+    EFFT_ERR_SIZE = -1,      /* n is not 2^q with 0 <= q <= EFFT_MAX_LOG2N */
+    EFFT_ERR_DTYPE = -2,     /* dtype is neither EFFT_C64 nor EFFT_C128 */
+    EFFT_ERR_DIR = -3,       /* dir is neither EFFT_FORWARD nor EFFT_BACKWARD */
+    EFFT_ERR_NULLPTR = -4,   /* a required pointer is NULL */
+    EFFT_ERR_ALIGN = -5,     /* a data pointer is not aligned to one element */
+    EFFT_ERR_PLAN_KIND = -6, /* efft_exec on an out-of-place plan or the reverse */
+    EFFT_ERR_OVERLAP = -7,   /* out-of-place input and output ranges overlap */
+    EFFT_ERR_ALLOC = -8,     /* device allocation for the plan failed */
+    EFFT_ERR_HIP = -9,       /* a HIP call or kernel launch failed */
+    EFFT_ERR_BADPLAN = -10,  /* handle is not a live plan (never made, or destroyed) */
+    EFFT_ERR_ARG = -11       /* any other invalid argument */
+};
+
+/* largest supported q: 2^34 complex64 (128 GiB) is the largest enormous
+ * transform that fits one 288 GB device in place */
+#define EFFT_MAX_LOG2N 34
+
+/*
+ * Create a plan for an N-point transform.  n = N = 2^q (0 <= q <= 34);
+ * dtype = EFFT_C64 or EFFT_C128; dir = EFFT_FORWARD or EFFT_BACKWARD;
+ * inplace != 0 makes an in-place plan (executed with efft_exec), inplace == 0
+ * an out-of-place plan (executed with efft_exec_oop).  Builds the FP64 twiddle
+ * tables on the current device and waits for that to finish.  Returns NULL on
+ * failure, with the reason in efft_last_error().
+ */
+efft_plan_t *efft_plan(int64_t n, int dtype, int dir, int inplace);
+
+/*
+ * As efft_plan, with every output multiplied by `scale` inside the last
+ * sub-FFT pass (no extra pass over the data).  scale = 1/N turns the
+ * backward transform into the inverse DFT; for N = 2^q that factor is exact.
+ * scale must be finite and nonzero (else EFFT_ERR_ARG).
+ */
+efft_plan_t *efft_plan_scaled(int64_t n, int dtype, int dir, int inplace, double scale);
+
+/*
+ * In-place transform of data[0 .. N) (device pointer, N elements of the
+ * plan's dtype), enqueued on stream.  The in-place path is a sequence of
+ * batched sub-FFT passes followed by one tiled digit-reversal pass; it needs
+ * no memory beyond the data array itself.
+ */
+int efft_exec(const efft_plan_t *plan, void *data, void *stream);
+
+/*
+ * Out-of-place transform: reads in[0 .. N), writes out[0 .. N), enqueued on
+ * stream.  in is never written (the input is preserved, as the paper's
+ * EFFT_Transform keeps Data() separate from Result(), Section 4).  The two
+ * ranges must not overlap.
+ */
+int efft_exec_oop(const efft_plan_t *plan, const void *in, void *out, void *stream);
+
+/*
+ * Same work as efft_exec (in == out, in-place plan) or efft_exec_oop (other
+ * plans), additionally recording events[i] (hipEvent_t, created by the
+ * caller) on stream just before kernel pass i and events[npass] after the
+ * last one, so that per-pass durations can be read with
+ * hipEventElapsedTime.  nevents must be at least efft_plan_passes(plan) + 1.
+ */
+int efft_exec_events(const efft_plan_t *plan, const void *in, void *out, void *stream,
+                     void **events, int nevents);
+
+/* Free the plan's device tables; NULL is a no-op returning EFFT_OK; a handle
+ * that is not a live plan (already destroyed) returns EFFT_ERR_BADPLAN. */
+int efft_destroy(efft_plan_t *plan);
+
+/* Status of the last efft_plan call on this host thread. */
+int efft_last_error(void);
+
+/* Static, human-readable name of a status code. */
+const char *efft_strerror(int status);
+
+/* Device bytes held by the plan (its twiddle tables); -1 for a bad handle. */
+int64_t efft_plan_bytes(const efft_plan_t *plan);
+
+/* Number of kernel launches one execution enqueues; -1 for a bad handle. */
+int efft_plan_passes(const efft_plan_t *plan);
+
+/*
+ * Host-only description of the decomposition a plan would use (no device
+ * needed).  Writes the digit sizes log2(R_1), ..., log2(R_m) of
+ * N = R_1 * ... * R_m (R_1 is the digit of the slowest-varying input index,
+ * transformed first) into log2_radix[0 .. m), at most max_digits of them, and
+ * returns m, or a negative status for invalid arguments.  *passes receives the
+ * number of kernel launches (m sub-FFT passes, plus one digit-reversal pass
+ * for in-place plans with m >= 2).
+ */
+int efft_schedule(int64_t n, int dtype, int inplace, int *log2_radix, int max_digits,
+                  int *passes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EFFT_H */

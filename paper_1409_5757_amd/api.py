@@ -1,0 +1,179 @@
+"""Python front end of the gfx950 FFT library (argument marshalling only).
+
+``fft(x)``   forward transform of Eq. "eqf" (paper, Section 1) along the last
+             dimension: F_k = sum_n x_n exp(-2*pi*i*k*n/N), unnormalised.
+``bfft(x)``  backward (conjugate-sign) transform, unnormalised: the adjoint.
+``ifft(x)``  inverse DFT = bfft(x) / N; the 1/N = 2^-q factor is applied
+             inside the library's last pass and is exact.
+
+Inputs are complex64 / complex128 CUDA tensors whose last dimension is a
+power of two (N = 2^q, q <= 34).  Leading dimensions are a batch of
+independent transforms.  All work runs in ``libefft.so`` on the tensor's
+device, on the current torch stream; there is no CPU fallback.
+
+``EfftFFT`` is the differentiable form: for the C-linear map y = s * A x its
+backward applies s * A^H, the transform of the opposite direction with the
+same scale, to the incoming gradient (PyTorch's convention for complex
+autograd: grad_x = A^H grad_y).
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+
+import torch
+
+from . import _lib
+from ._lib import EFFT_BACKWARD, EFFT_C64, EFFT_C128, EFFT_FORWARD, EfftError
+
+_DTYPES = {torch.complex64: EFFT_C64, torch.complex128: EFFT_C128}
+
+
+class Plan:
+    """One committed transform (size, dtype, direction, in/out of place, scale)."""
+
+    def __init__(self, n: int, dtype: torch.dtype, direction: int = EFFT_FORWARD,
+                 inplace: bool = False, scale: float = 1.0, device=None):
+        if dtype not in _DTYPES:
+            raise TypeError(f"dtype must be torch.complex64 or torch.complex128, got {dtype}")
+        self.lib = _lib.load()
+        self.n = int(n)
+        self.dtype = dtype
+        self.direction = int(direction)
+        self.inplace = bool(inplace)
+        self.scale = float(scale)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        with torch.cuda.device(self.device):
+            h = self.lib.efft_plan_scaled(self.n, _DTYPES[dtype], self.direction,
+                                          int(self.inplace), self.scale)
+        if not h:
+            raise EfftError(self.lib.efft_last_error(), "efft_plan")
+        self.handle = ctypes.c_void_p(h)
+        self.passes = self.lib.efft_plan_passes(self.handle)
+
+    def _check(self, t: torch.Tensor, name: str):
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name}: expected {self.dtype}, got {t.dtype}")
+        if t.device != self.device:
+            raise ValueError(f"{name}: expected a tensor on {self.device}, got {t.device}")
+        if t.shape[-1] != self.n:
+            raise ValueError(f"{name}: last dimension {t.shape[-1]} != plan size {self.n}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: tensor must be contiguous")
+
+    def execute(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Transform every length-N row of x; in place for in-place plans."""
+        self._check(x, "input")
+        s = ctypes.c_void_p((stream or torch.cuda.current_stream(self.device)).cuda_stream)
+        rows = x.numel() // self.n if self.n else 0
+        xp = x.data_ptr()
+        step = self.n * x.element_size()
+        if self.inplace:
+            for r in range(rows):
+                _lib.check(self.lib.efft_exec(self.handle, ctypes.c_void_p(xp + r * step), s), "efft_exec")
+            return x
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(out, "output")
+        op = out.data_ptr()
+        for r in range(rows):
+            _lib.check(self.lib.efft_exec_oop(self.handle, ctypes.c_void_p(xp + r * step),
+                                              ctypes.c_void_p(op + r * step), s), "efft_exec_oop")
+        return out
+
+    def execute_events(self, x: torch.Tensor, out: torch.Tensor, events, stream=None) -> None:
+        """One transform of a single signal, recording caller-created hipEvents
+        before each pass and after the last (``len(events) == passes + 1``)."""
+        s = ctypes.c_void_p((stream or torch.cuda.current_stream(self.device)).cuda_stream)
+        arr = (ctypes.c_void_p * len(events))(*events)
+        _lib.check(self.lib.efft_exec_events(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr()), s, arr, len(events)),
+                   "efft_exec_events")
+
+    def device_bytes(self) -> int:
+        return int(self.lib.efft_plan_bytes(self.handle))
+
+    def close(self) -> None:
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.efft_destroy(h)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order varies
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_cache: dict = {}
+_cache_lock = threading.Lock()
+
+
+def get_plan(n: int, dtype: torch.dtype, direction: int, inplace: bool, scale: float,
+             device: torch.device) -> Plan:
+    """Cached plan keyed by (N, dtype, direction, in place, scale, device)."""
+    key = (int(n), dtype, int(direction), bool(inplace), float(scale), device)
+    with _cache_lock:
+        p = _cache.get(key)
+        if p is None:
+            p = Plan(n, dtype, direction, inplace, scale, device)
+            _cache[key] = p
+        return p
+
+
+def clear_plan_cache() -> None:
+    with _cache_lock:
+        for p in _cache.values():
+            p.close()
+        _cache.clear()
+
+
+def _transform(x: torch.Tensor, direction: int, scale: float, inplace: bool,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    if not x.is_cuda:
+        raise ValueError("efft transforms run on the GPU only; got a CPU tensor")
+    if x.dtype not in _DTYPES:
+        raise TypeError(f"dtype must be complex64 or complex128, got {x.dtype}")
+    n = x.shape[-1]
+    p = get_plan(n, x.dtype, direction, inplace, scale, x.device)
+    if inplace:
+        return p.execute(x)
+    return p.execute(x.contiguous(), out=out)
+
+
+class EfftFFT(torch.autograd.Function):
+    """y = scale * A_dir x, differentiable; backward applies scale * A_{-dir}."""
+
+    @staticmethod
+    def forward(ctx, x, direction: int = EFFT_FORWARD, scale: float = 1.0):
+        ctx.direction = direction
+        ctx.scale = scale
+        return _transform(x, direction, scale, inplace=False)
+
+    @staticmethod
+    def backward(ctx, g):
+        return _transform(g.contiguous(), -ctx.direction, ctx.scale, inplace=False), None, None
+
+
+def fft(x: torch.Tensor, inplace: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Forward DFT along the last dimension (sign -1, unnormalised)."""
+    if not inplace and torch.is_grad_enabled() and x.requires_grad:
+        return EfftFFT.apply(x, EFFT_FORWARD, 1.0)
+    return _transform(x, EFFT_FORWARD, 1.0, inplace, out)
+
+
+def bfft(x: torch.Tensor, inplace: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Backward DFT along the last dimension (sign +1, unnormalised)."""
+    if not inplace and torch.is_grad_enabled() and x.requires_grad:
+        return EfftFFT.apply(x, EFFT_BACKWARD, 1.0)
+    return _transform(x, EFFT_BACKWARD, 1.0, inplace, out)
+
+
+def ifft(x: torch.Tensor, inplace: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Inverse DFT along the last dimension: bfft(x) / N."""
+    scale = 1.0 / x.shape[-1]
+    if not inplace and torch.is_grad_enabled() and x.requires_grad:
+        return EfftFFT.apply(x, EFFT_BACKWARD, scale)
+    return _transform(x, EFFT_BACKWARD, scale, inplace, out)

@@ -1,0 +1,513 @@
+// efft_api.hip -- planner, executor and C ABI (include/efft.h).
+//
+// Decomposition.  N = 2^q is split into digits N = R_1 * ... * R_m, R_1 the
+// digit of the slowest-varying input index.  Each pass transforms one digit
+// with batched L = R_j point sub-FFTs (a multi-radix generalisation of the
+// radix-2 split of Section 2.2, Eqs. "eqct"/"eqctt"; the paper's
+// scatter -> bin DFTs -> reassembly stages of Section 2.3 are the same
+// factorisation with R = 2 reassembly levels).
+//
+// In place (decimation in frequency): pass j works inside blocks of
+// B_j = R_j...R_m points on lines of stride s_j = R_{j+1}...R_m, multiplying
+// output k_j of line o by W_{B_j}^{o*k_j}.  The result is in digit-reversed
+// order; the digits are chosen palindromic (R_j = R_{m+1-j}) so that the
+// reversal is an involution, done in place by one pass that swaps tile pairs
+// (the read-set = write-set idea of the paper's pair reassembly, Section 3.4).
+//
+// Out of place: the first pass reads x along the slowest digit and writes
+// each transformed line as a contiguous row of `out` at a digit-reversed row
+// index; later passes then work in place on `out` along strided columns and
+// leave natural order, so no reordering pass is needed.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <new>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/efft.h"
+#include "efft_internal.hpp"
+
+using namespace efft;
+
+namespace {
+
+constexpr uint64_t PLAN_MAGIC = 0x45464654504c414eULL;  // "EFFTPLAN"
+constexpr int MAX_DIGITS = 6;
+
+struct Pass {
+    bool swap;
+    int layout, logl, lines;
+    StageParams sp;  // src/dst filled at exec time
+    SwapParams wp;   // data filled at exec time
+};
+
+thread_local int g_last_error = EFFT_OK;
+std::mutex g_reg_mu;
+std::unordered_set<const void *> g_registry;
+
+bool registered(const void *p)
+{
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    return g_registry.count(p) != 0;
+}
+
+// largest line (log2) per layout: strided lines are limited by LDS for a
+// W-line tile, contiguous lines by LDS for one line
+int col_max(int dtype_bytes) { return dtype_bytes == 16 ? 10 : 10; }
+int row_max(int dtype_bytes) { return dtype_bytes == 16 ? 12 : 12; }
+
+int log2_exact(int64_t n)
+{
+    if (n <= 0 || (n & (n - 1)) != 0) return -1;
+    int q = 0;
+    while ((int64_t(1) << q) < n) ++q;
+    return q;
+}
+
+// Balanced palindromic digits for the in-place plan.
+int plan_digits_inplace(int q, int eb, int *d)
+{
+    if (q <= row_max(eb)) {
+        d[0] = q;
+        return 1;
+    }
+    const int cm = col_max(eb);
+    for (int m = 2; m <= MAX_DIGITS; ++m) {
+        const int half = m / 2, center = m % 2;
+        // search all palindromes of this length; keep the one with the
+        // smallest largest digit, ties to the larger outer digit
+        int best_max = 1 << 30, best[MAX_DIGITS] = {0};
+        bool found = false;
+        int dig[MAX_DIGITS];
+        // enumerate the first `half` digits and the center in [4, cm]: every
+        // strided pass then has lines of at least 16 points and a stride of at
+        // least 16 lines
+        int total = 1;
+        for (int i = 0; i < half; ++i) total *= (cm - 3);
+        for (int idx = 0; idx < total; ++idx) {
+            int rem = idx, sum = 0;
+            for (int i = 0; i < half; ++i) {
+                dig[i] = 4 + rem % (cm - 3);
+                rem /= (cm - 3);
+                dig[m - 1 - i] = dig[i];
+                sum += 2 * dig[i];
+            }
+            if (center) {
+                const int c = q - sum;
+                if (c < 4 || c > cm) continue;
+                dig[half] = c;
+            } else if (sum != q) {
+                continue;
+            }
+            int mx = 0;
+            for (int i = 0; i < m; ++i) mx = dig[i] > mx ? dig[i] : mx;
+            if (mx < best_max || (mx == best_max && dig[0] > best[0])) {
+                best_max = mx;
+                for (int i = 0; i < m; ++i) best[i] = dig[i];
+                found = true;
+            }
+        }
+        if (found) {
+            for (int i = 0; i < m; ++i) d[i] = best[i];
+            return m;
+        }
+    }
+    return -1;
+}
+
+// Balanced digits for the out-of-place plan (every digit >= 4 when m > 1).
+int plan_digits_oop(int q, int eb, int *d)
+{
+    if (q <= row_max(eb)) {
+        d[0] = q;
+        return 1;
+    }
+    const int cm = col_max(eb);
+    int m = (q + cm - 1) / cm;
+    if (m < 2) m = 2;
+    if (m > MAX_DIGITS) return -1;
+    for (int i = 0; i < m; ++i) d[i] = q / m + (i < q % m ? 1 : 0);
+    return m;
+}
+
+int plan_digits(int q, int eb, int inplace, int *d)
+{
+    return inplace ? plan_digits_inplace(q, eb, d) : plan_digits_oop(q, eb, d);
+}
+
+int dtype_bytes(int dtype) { return dtype == EFFT_C128 ? 16 : dtype == EFFT_C64 ? 8 : 0; }
+
+}  // namespace
+
+struct efft_plan_s {
+    uint64_t magic;
+    int64_t n;
+    int q, dtype, dir, inplace, eb;
+    int m;
+    int digits[MAX_DIGITS];
+    std::vector<Pass> passes;
+    double scale;
+    double2 *tables;
+    int64_t table_bytes;
+};
+
+namespace {
+
+StageParams base_params(const efft_plan_s *p, const TwTable &tt)
+{
+    StageParams sp{};
+    sp.tt = tt;
+    sp.conj = p->dir == EFFT_BACKWARD ? 1 : 0;
+    sp.twmode = TW_NONE;
+    sp.rev.nd = 0;
+    sp.scale = 1.0;
+    sp.apply_scale = 0;
+    return sp;
+}
+
+void build_passes_unscaled(efft_plan_s *p, const TwTable &tt);
+
+// The output scale is applied by the last sub-FFT pass (a trailing
+// digit-reversal pass only permutes).
+void build_passes(efft_plan_s *p, const TwTable &tt)
+{
+    build_passes_unscaled(p, tt);
+    if (p->scale != 1.0) {
+        for (size_t i = p->passes.size(); i-- > 0;) {
+            if (!p->passes[i].swap) {
+                p->passes[i].sp.apply_scale = 1;
+                p->passes[i].sp.scale = p->scale;
+                break;
+            }
+        }
+    }
+}
+
+void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
+{
+    const int64_t n = p->n;
+    const int m = p->m;
+    const int *d = p->digits;
+    p->passes.clear();
+    if (p->inplace) {
+        for (int j = 0; j < m; ++j) {
+            Pass ps{};
+            ps.swap = false;
+            ps.logl = d[j];
+            const int64_t L = int64_t(1) << d[j];
+            int64_t s = 1;
+            for (int i = j + 1; i < m; ++i) s <<= d[i];
+            ps.sp = base_params(p, tt);
+            ps.sp.s = s;
+            ps.sp.B = s * L;
+            ps.sp.n_over_l = uint64_t(n / L);
+            if (s == 1) {
+                ps.layout = LAYOUT_ROW;
+                ps.lines = row_lines(p->eb, d[j], n / L);
+            } else {
+                ps.layout = LAYOUT_COL;
+                ps.lines = col_lines(p->eb);
+                ps.sp.twmode = TW_OFFSET;
+                ps.sp.tw_scale = uint64_t(n / (s * L));
+            }
+            ps.sp.ntiles = (n / L) / ps.lines;
+            p->passes.push_back(ps);
+        }
+        if (m >= 2) {
+            Pass ps{};
+            ps.swap = true;
+            ps.wp.R = int64_t(1) << d[0];
+            int64_t M = 1;
+            ps.wp.mid.nd = 0;
+            for (int i = m - 2; i >= 1; --i) {  // lowest digit first
+                ps.wp.mid.bits[ps.wp.mid.nd++] = d[i];
+                M <<= d[i];
+            }
+            ps.wp.M = M;
+            const int64_t ts = ps.wp.R < 32 ? ps.wp.R : 32;
+            ps.wp.nt = ps.wp.R / ts;
+            p->passes.push_back(ps);
+        }
+        return;
+    }
+    // out of place
+    if (m == 1) {
+        Pass ps{};
+        ps.swap = false;
+        ps.logl = d[0];
+        ps.layout = LAYOUT_ROW;
+        ps.lines = row_lines(p->eb, d[0], 1);
+        ps.sp = base_params(p, tt);
+        ps.sp.s = 1;
+        ps.sp.B = n;
+        ps.sp.n_over_l = 1;
+        ps.sp.ntiles = 1;
+        p->passes.push_back(ps);
+        return;
+    }
+    {  // first pass: lines along digit 1, rows written at R_1 * rev(o)
+        Pass ps{};
+        ps.swap = false;
+        ps.logl = d[0];
+        ps.layout = LAYOUT_COL2ROW;
+        ps.lines = col_lines(p->eb);
+        const int64_t L = int64_t(1) << d[0];
+        ps.sp = base_params(p, tt);
+        ps.sp.s = n / L;
+        ps.sp.B = n;
+        ps.sp.n_over_l = uint64_t(n / L);
+        ps.sp.tw_scale = 1;
+        ps.sp.row_mul = L;
+        ps.sp.rev.nd = 0;
+        for (int i = m - 1; i >= 1; --i) ps.sp.rev.bits[ps.sp.rev.nd++] = d[i];  // o = n_m + R_m n_{m-1} + ...
+        ps.sp.ntiles = (n / L) / ps.lines;
+        p->passes.push_back(ps);
+    }
+    int64_t C = int64_t(1) << d[0];
+    for (int j = 1; j < m; ++j) {
+        Pass ps{};
+        ps.swap = false;
+        ps.logl = d[j];
+        ps.layout = LAYOUT_COL;
+        ps.lines = col_lines(p->eb);
+        const int64_t L = int64_t(1) << d[j];
+        ps.sp = base_params(p, tt);
+        ps.sp.s = C;
+        ps.sp.B = C * L;
+        ps.sp.n_over_l = uint64_t(n / L);
+        if (j + 1 < m) {
+            ps.sp.twmode = TW_REVBLOCK;
+            ps.sp.tw_scale = uint64_t(C);
+            ps.sp.rev.nd = 0;
+            for (int i = j + 1; i < m; ++i) ps.sp.rev.bits[ps.sp.rev.nd++] = d[i];  // H = n_{j+1} + ...
+        }
+        ps.sp.ntiles = (n / L) / ps.lines;
+        p->passes.push_back(ps);
+        C *= L;
+    }
+}
+
+int validate_ptr(const efft_plan_s *p, const void *ptr)
+{
+    if (!ptr) return EFFT_ERR_NULLPTR;
+    if (reinterpret_cast<uintptr_t>(ptr) % uintptr_t(p->eb) != 0) return EFFT_ERR_ALIGN;
+    return EFFT_OK;
+}
+
+int run(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events,
+        int nevents)
+{
+    if (events && nevents < int(p->passes.size()) + 1) return EFFT_ERR_ARG;
+    for (size_t i = 0; i < p->passes.size(); ++i) {
+        Pass ps = p->passes[i];
+        if (events && hipEventRecord(static_cast<hipEvent_t>(events[i]), stream) != hipSuccess)
+            return EFFT_ERR_HIP;
+        hipError_t e;
+        if (ps.swap) {
+            ps.wp.data = out;
+            e = launch_swap(p->eb, ps.wp, stream);
+        } else {
+            // the first pass reads the input; every later pass works in place on out
+            ps.sp.src = (i == 0) ? in : out;
+            ps.sp.dst = out;
+            e = launch_stage(p->eb, ps.layout, ps.logl, ps.lines, ps.sp, stream);
+        }
+        if (e != hipSuccess) return EFFT_ERR_HIP;
+    }
+    if (events && hipEventRecord(static_cast<hipEvent_t>(events[p->passes.size()]), stream) != hipSuccess)
+        return EFFT_ERR_HIP;
+    return EFFT_OK;
+}
+
+const efft_plan_s *live(const efft_plan_t *plan)
+{
+    if (!plan || !registered(plan)) return nullptr;
+    return plan->magic == PLAN_MAGIC ? plan : nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+efft_plan_t *efft_plan(int64_t n, int dtype, int dir, int inplace)
+{
+    return efft_plan_scaled(n, dtype, dir, inplace, 1.0);
+}
+
+efft_plan_t *efft_plan_scaled(int64_t n, int dtype, int dir, int inplace, double scale)
+{
+    const int q = log2_exact(n);
+    if (q < 0 || q > EFFT_MAX_LOG2N) {
+        g_last_error = EFFT_ERR_SIZE;
+        return nullptr;
+    }
+    const int eb = dtype_bytes(dtype);
+    if (!eb) {
+        g_last_error = EFFT_ERR_DTYPE;
+        return nullptr;
+    }
+    if (dir != EFFT_FORWARD && dir != EFFT_BACKWARD) {
+        g_last_error = EFFT_ERR_DIR;
+        return nullptr;
+    }
+    if (!(scale == scale) || scale == 0.0 || scale - scale != 0.0) {  // NaN, zero or infinite
+        g_last_error = EFFT_ERR_ARG;
+        return nullptr;
+    }
+    efft_plan_s *p = new (std::nothrow) efft_plan_s();
+    if (!p) {
+        g_last_error = EFFT_ERR_ALLOC;
+        return nullptr;
+    }
+    p->magic = PLAN_MAGIC;
+    p->n = n;
+    p->q = q;
+    p->dtype = dtype;
+    p->dir = dir;
+    p->inplace = inplace ? 1 : 0;
+    p->eb = eb;
+    p->scale = scale;
+    p->m = plan_digits(q, eb, p->inplace, p->digits);
+    if (p->m < 1) {
+        delete p;
+        g_last_error = EFFT_ERR_SIZE;
+        return nullptr;
+    }
+    // two-level FP64 table: lo[2^h], hi[2^(q-h)], h = ceil(q/2)
+    const int h = (q + 1) / 2;
+    const int64_t n_lo = int64_t(1) << h, n_hi = int64_t(1) << (q - h);
+    p->table_bytes = (n_lo + n_hi) * int64_t(sizeof(double2));
+    if (hipMalloc(reinterpret_cast<void **>(&p->tables), size_t(p->table_bytes)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        g_last_error = EFFT_ERR_ALLOC;
+        return nullptr;
+    }
+    if (launch_twiddle_table(p->tables, n_lo, p->tables + n_lo, n_hi, h, q, nullptr) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(p->tables);
+        delete p;
+        g_last_error = EFFT_ERR_HIP;
+        return nullptr;
+    }
+    TwTable tt;
+    tt.lo = p->tables;
+    tt.hi = p->tables + n_lo;
+    tt.h = h;
+    tt.mask_n = uint64_t(n) - 1u;
+    tt.mask_lo = uint64_t(n_lo) - 1u;
+    build_passes(p, tt);
+    {
+        std::lock_guard<std::mutex> lk(g_reg_mu);
+        g_registry.insert(p);
+    }
+    g_last_error = EFFT_OK;
+    return p;
+}
+
+int efft_exec(const efft_plan_t *plan, void *data, void *stream)
+{
+    const efft_plan_s *p = live(plan);
+    if (!p) return plan ? EFFT_ERR_BADPLAN : EFFT_ERR_NULLPTR;
+    if (!p->inplace) return EFFT_ERR_PLAN_KIND;
+    const int v = validate_ptr(p, data);
+    if (v != EFFT_OK) return v;
+    return run(p, data, data, static_cast<hipStream_t>(stream), nullptr, 0);
+}
+
+int efft_exec_oop(const efft_plan_t *plan, const void *in, void *out, void *stream)
+{
+    const efft_plan_s *p = live(plan);
+    if (!p) return plan ? EFFT_ERR_BADPLAN : EFFT_ERR_NULLPTR;
+    if (p->inplace) return EFFT_ERR_PLAN_KIND;
+    int v = validate_ptr(p, in);
+    if (v == EFFT_OK) v = validate_ptr(p, out);
+    if (v != EFFT_OK) return v;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+    const uintptr_t bytes = uintptr_t(p->n) * uintptr_t(p->eb);
+    if (a < b + bytes && b < a + bytes) return EFFT_ERR_OVERLAP;
+    return run(p, in, out, static_cast<hipStream_t>(stream), nullptr, 0);
+}
+
+int efft_exec_events(const efft_plan_t *plan, const void *in, void *out, void *stream, void **events,
+                     int nevents)
+{
+    const efft_plan_s *p = live(plan);
+    if (!p) return plan ? EFFT_ERR_BADPLAN : EFFT_ERR_NULLPTR;
+    if (!events) return EFFT_ERR_NULLPTR;
+    int v = validate_ptr(p, in);
+    if (v == EFFT_OK) v = validate_ptr(p, out);
+    if (v != EFFT_OK) return v;
+    if (p->inplace && in != out) return EFFT_ERR_PLAN_KIND;
+    if (!p->inplace) {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+        const uintptr_t bytes = uintptr_t(p->n) * uintptr_t(p->eb);
+        if (a < b + bytes && b < a + bytes) return EFFT_ERR_OVERLAP;
+    }
+    return run(p, in, out, static_cast<hipStream_t>(stream), events, nevents);
+}
+
+int efft_destroy(efft_plan_t *plan)
+{
+    if (!plan) return EFFT_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_reg_mu);
+        if (!g_registry.erase(plan)) return EFFT_ERR_BADPLAN;
+    }
+    plan->magic = 0;
+    const hipError_t e = hipFree(plan->tables);
+    delete plan;
+    return e == hipSuccess ? EFFT_OK : EFFT_ERR_HIP;
+}
+
+int efft_last_error(void) { return g_last_error; }
+
+const char *efft_strerror(int status)
+{
+    switch (status) {
+    case EFFT_OK: return "EFFT_OK: success";
+    case EFFT_ERR_SIZE: return "EFFT_ERR_SIZE: n must be 2^q with 0 <= q <= 34";
+    case EFFT_ERR_DTYPE: return "EFFT_ERR_DTYPE: dtype must be EFFT_C64 or EFFT_C128";
+    case EFFT_ERR_DIR: return "EFFT_ERR_DIR: dir must be EFFT_FORWARD (-1) or EFFT_BACKWARD (+1)";
+    case EFFT_ERR_NULLPTR: return "EFFT_ERR_NULLPTR: required pointer is NULL";
+    case EFFT_ERR_ALIGN: return "EFFT_ERR_ALIGN: data pointer not aligned to one element";
+    case EFFT_ERR_PLAN_KIND: return "EFFT_ERR_PLAN_KIND: in-place/out-of-place mismatch";
+    case EFFT_ERR_OVERLAP: return "EFFT_ERR_OVERLAP: input and output ranges overlap";
+    case EFFT_ERR_ALLOC: return "EFFT_ERR_ALLOC: device allocation failed";
+    case EFFT_ERR_HIP: return "EFFT_ERR_HIP: HIP call or kernel launch failed";
+    case EFFT_ERR_BADPLAN: return "EFFT_ERR_BADPLAN: not a live plan";
+    case EFFT_ERR_ARG: return "EFFT_ERR_ARG: invalid argument";
+    default: return "unknown efft status";
+    }
+}
+
+int64_t efft_plan_bytes(const efft_plan_t *plan)
+{
+    const efft_plan_s *p = live(plan);
+    return p ? p->table_bytes : -1;
+}
+
+int efft_plan_passes(const efft_plan_t *plan)
+{
+    const efft_plan_s *p = live(plan);
+    return p ? int(p->passes.size()) : -1;
+}
+
+int efft_schedule(int64_t n, int dtype, int inplace, int *log2_radix, int max_digits, int *passes)
+{
+    const int q = log2_exact(n);
+    if (q < 0 || q > EFFT_MAX_LOG2N) return EFFT_ERR_SIZE;
+    const int eb = dtype_bytes(dtype);
+    if (!eb) return EFFT_ERR_DTYPE;
+    if (!log2_radix || !passes) return EFFT_ERR_NULLPTR;
+    int d[MAX_DIGITS];
+    const int m = plan_digits(q, eb, inplace ? 1 : 0, d);
+    if (m < 1) return EFFT_ERR_SIZE;
+    if (m > max_digits) return EFFT_ERR_ARG;
+    for (int i = 0; i < m; ++i) log2_radix[i] = d[i];
+    *passes = m + ((inplace && m >= 2) ? 1 : 0);
+    return m;
+}
+
+}  // extern "C"

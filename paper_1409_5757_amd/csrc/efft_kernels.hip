@@ -1,0 +1,412 @@
+// efft_kernels.hip -- gfx950 kernels of the decomposed 1D FFT.
+//
+// The length-N transform is split N = R_1 * ... * R_m (Cooley-Tukey, the
+// radix-2 split of Section 2.2 applied with larger radices); each pass runs
+// batched sub-FFTs of one length L = R_j along one digit of the index.  A
+// pass is one read and one write of the whole array.  Inside a workgroup a
+// line of L points is transformed by the Stockham autosort variant of
+// Cooley-Tukey: every thread holds E = 16 points of its line in registers,
+// does radix-16 (and one smaller-radix) butterflies, and exchanges through
+// LDS between steps, so the line comes out in natural order.  Thread t of a
+// line always holds points t + P*i (P = L/16 threads per line, i < 16) both
+// when loading and when storing, which makes global accesses coalesced in
+// either layout: along the line for contiguous lines, across W adjacent lines
+// (one 128-byte segment per row) for strided lines.
+#include <hip/hip_runtime.h>
+
+#include "efft_internal.hpp"
+
+namespace efft {
+
+// LDS index of point p of a line: one padding slot per 16 points breaks the
+// power-of-two strides of the Stockham writes across banks
+__device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
+
+template <int L> struct LineGeom {
+    static constexpr int E = L >= 16 ? 16 : L;  // points per thread
+    static constexpr int P = L / E;             // threads per line
+    static constexpr int PADDED = L + (L >> 4) + 2;  // padded line stride in LDS
+};
+
+// Radix of Stockham step `st` for a line of 2^LOGL points: a leading step of
+// radix 2^(LOGL mod 4) when that is not 0, then radix-16 steps.
+template <int LOGL> struct Radices {
+    static constexpr int LEAD = (LOGL < 4) ? LOGL : (LOGL % 4);
+    static constexpr int NSTEPS = (LOGL < 4) ? 1 : (LOGL / 4 + (LEAD ? 1 : 0));
+    static constexpr int radix(int st)
+    {
+        if (LOGL < 4) return 1 << LOGL;
+        if (LEAD && st == 0) return 1 << LEAD;
+        return 16;
+    }
+    static constexpr int span(int st)  // product of the radices before step st
+    {
+        int s = 1;
+        for (int i = 0; i < st; ++i) s *= radix(i);
+        return s;
+    }
+};
+
+// One Stockham step on the thread's E registers.  Butterfly j = t + P*b
+// (b < E/R) takes points j + (L/R)*r, i.e. registers b + (E/R)*r; after the
+// twiddle W_{NS*R}^{(j mod NS)*r} and an R-point DFT, output r goes to line
+// position (j/NS)*NS*R + (j mod NS) + NS*r -- into LDS, or, on the last step
+// (where that position is j + (L/R)*r), back into register b + (E/R)*r.
+template <typename V, int L, int R, int NS, bool TO_LDS>
+__device__ __forceinline__ void stockham_step(V *v, V *lds_line, int t, const TwTable &tt,
+                                              uint64_t n_over_l)
+{
+    constexpr int E = LineGeom<L>::E;
+    constexpr int P = LineGeom<L>::P;
+    constexpr int NB = E / R;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + P * b;
+        V u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[b + NB * r];
+        if constexpr (NS > 1) {
+            const int jm = j & (NS - 1);
+            // W_{NS*R}^{jm} = W_N^{jm * N/(NS*R)}
+            const uint64_t m = uint64_t(jm) * (n_over_l * uint64_t(L / (NS * R)));
+            double2 p[R];
+            powers<R>(tw_lookup(tt, m), p);
+#pragma unroll
+            for (int r = 1; r < R; ++r) u[r] = cmul(u[r], round_tw<V>(p[r]));
+        }
+        dft<R>(u);
+        if constexpr (TO_LDS) {
+            const int base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds_line[lds_pad(base + NS * r)] = u[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b + NB * r] = u[r];
+        }
+    }
+}
+
+template <typename V, int L>
+__device__ __forceinline__ void lds_gather(V *v, const V *lds_line, int t)
+{
+    constexpr int E = LineGeom<L>::E;
+    constexpr int P = LineGeom<L>::P;
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = lds_line[lds_pad(t + P * i)];
+}
+
+// All Stockham steps of a line of 2^LOGL points.  On entry v holds input
+// points t + P*i; on exit outputs k = t + P*i (FINAL_TO_LDS: the outputs are
+// left in LDS at natural positions instead).
+template <typename V, int LOGL, bool FINAL_TO_LDS>
+__device__ __forceinline__ void line_fft(V *v, V *lds_line, int t, const TwTable &tt,
+                                         uint64_t n_over_l)
+{
+    constexpr int L = 1 << LOGL;
+    using Rd = Radices<LOGL>;
+    constexpr int NST = Rd::NSTEPS;
+    static_assert(NST <= 4, "line too long");
+    // step 0
+    if constexpr (NST == 1) {
+        stockham_step<V, L, Rd::radix(0), 1, FINAL_TO_LDS>(v, lds_line, t, tt, n_over_l);
+        return;
+    } else {
+        stockham_step<V, L, Rd::radix(0), 1, true>(v, lds_line, t, tt, n_over_l);
+        __syncthreads();
+        lds_gather<V, L>(v, lds_line, t);
+        __syncthreads();
+        if constexpr (NST == 2) {
+            stockham_step<V, L, Rd::radix(1), Rd::span(1), FINAL_TO_LDS>(v, lds_line, t, tt, n_over_l);
+        } else {
+            stockham_step<V, L, Rd::radix(1), Rd::span(1), true>(v, lds_line, t, tt, n_over_l);
+            __syncthreads();
+            lds_gather<V, L>(v, lds_line, t);
+            __syncthreads();
+            if constexpr (NST == 3) {
+                stockham_step<V, L, Rd::radix(2), Rd::span(2), FINAL_TO_LDS>(v, lds_line, t, tt,
+                                                                             n_over_l);
+            } else {
+                stockham_step<V, L, Rd::radix(2), Rd::span(2), true>(v, lds_line, t, tt, n_over_l);
+                __syncthreads();
+                lds_gather<V, L>(v, lds_line, t);
+                __syncthreads();
+                stockham_step<V, L, Rd::radix(3), Rd::span(3), FINAL_TO_LDS>(v, lds_line, t, tt,
+                                                                             n_over_l);
+            }
+        }
+    }
+}
+
+// Multiply v[i] (output k = t + P*i of a line) by W_N^(g*k*scale): two table
+// lookups and a power ladder in FP64, rounded once to the storage type.
+template <typename V, int E, int P>
+__device__ __forceinline__ void apply_stage_twiddle(V *v, int t, uint64_t g, uint64_t scale,
+                                                    const TwTable &tt)
+{
+    const uint64_t gs = g * scale;
+    const double2 w0 = tw_lookup(tt, gs * uint64_t(t));
+    const double2 ws = tw_lookup(tt, gs * uint64_t(P));
+    double2 p[E];
+    powers<E>(ws, p);
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = cmul(v[i], round_tw<V>(cmul(w0, p[i])));
+}
+
+// Output scaling (last pass only) and the conjugation of the backward direction.
+template <typename V, int E>
+__device__ __forceinline__ void finish_outputs(V *v, const StageParams &sp)
+{
+    using T = decltype(V{}.x);
+    if (sp.apply_scale) {
+        const T f = T(sp.scale);
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = V{v[i].x * f, v[i].y * f};
+    }
+    if (sp.conj) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i].y = -v[i].y;
+    }
+}
+
+template <typename T, int LOGL, int LINES, int LAYOUT>
+__global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
+    stage_kernel(StageParams sp)
+{
+    using V = typename vec2<T>::type;
+    constexpr int L = 1 << LOGL;
+    constexpr int E = LineGeom<L>::E;
+    constexpr int P = LineGeom<L>::P;
+    constexpr int PADDED = LineGeom<L>::PADDED;
+    constexpr bool NEED_LDS = (Radices<LOGL>::NSTEPS > 1) || (LAYOUT == LAYOUT_COL2ROW);
+    __shared__ V lds[NEED_LDS ? LINES * PADDED : 1];
+
+    const int tid = threadIdx.x;
+    int c, t;
+    if constexpr (LAYOUT == LAYOUT_ROW) {
+        t = tid % P;
+        c = tid / P;
+    } else {
+        c = tid % LINES;
+        t = tid / LINES;
+    }
+    const int64_t line = int64_t(blockIdx.x) * LINES + c;
+    const int64_t blk = line / sp.s;
+    const int64_t o = line - blk * sp.s;
+    const int64_t base = blk * sp.B + o;
+    const V *src = static_cast<const V *>(sp.src);
+    V *dst = static_cast<V *>(sp.dst);
+
+    V v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = src[base + sp.s * int64_t(t + P * i)];
+    if (sp.conj) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i].y = -v[i].y;
+    }
+
+    V *lds_line = lds + (NEED_LDS ? c * PADDED : 0);
+    if constexpr (LAYOUT != LAYOUT_COL2ROW) {
+        line_fft<V, LOGL, false>(v, lds_line, t, sp.tt, sp.n_over_l);
+        if (sp.twmode != TW_NONE) {
+            const uint64_t g = sp.twmode == TW_OFFSET ? uint64_t(o) : digit_reverse(uint64_t(blk), sp.rev);
+            apply_stage_twiddle<V, E, P>(v, t, g, sp.tw_scale, sp.tt);
+        }
+        finish_outputs<V, E>(v, sp);
+#pragma unroll
+        for (int i = 0; i < E; ++i) dst[base + sp.s * int64_t(t + P * i)] = v[i];
+    } else {
+        // outputs land in LDS in natural order; re-read them one contiguous
+        // row per line and write that row at its digit-reversed position
+        line_fft<V, LOGL, true>(v, lds_line, t, sp.tt, sp.n_over_l);
+        __syncthreads();
+        const int t2 = tid % P;
+        const int c2 = tid / P;
+        const int64_t o2 = int64_t(blockIdx.x) * LINES + c2;  // one block: line == offset
+        const V *row_lds = lds + c2 * PADDED;
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = row_lds[lds_pad(t2 + P * i)];
+        apply_stage_twiddle<V, E, P>(v, t2, uint64_t(o2), sp.tw_scale, sp.tt);
+        finish_outputs<V, E>(v, sp);
+        const int64_t row = sp.row_mul * int64_t(digit_reverse(uint64_t(o2), sp.rev));
+#pragma unroll
+        for (int i = 0; i < E; ++i) dst[row + t2 + P * i] = v[i];
+    }
+}
+
+// ------------------------------------------------------------------- swap
+// Workgroup (I, J, mu) exchanges tile A = rows I*TS.., cols J*TS.. of slab mu
+// with tile B = rows J*TS.., cols I*TS.. of slab rev(mu), each transposed.
+// Each unordered pair is handled by the workgroup whose key is the smaller;
+// a tile paired with itself is transposed in place.  Every element is read
+// and written exactly once.
+template <typename T, int TS>
+__global__ void __launch_bounds__(256) swap_kernel(SwapParams p)
+{
+    using V = typename vec2<T>::type;
+    constexpr int NT = 256;
+    constexpr int ROWS_PER_PASS = NT / TS;
+    __shared__ V ta[TS][TS + 1];
+    __shared__ V tb[TS][TS + 1];
+
+    // grid: x = middle index mu (up to 2^24), y = tile pair I*nt + J (up to 1024)
+    const int64_t mu = blockIdx.x;
+    const int64_t ij = blockIdx.y;
+    const int64_t I = ij / p.nt;
+    const int64_t J = ij - I * p.nt;
+    const int64_t rmu = int64_t(digit_reverse(uint64_t(mu), p.mid));
+    const int64_t key = ij * p.M + mu;
+    const int64_t pkey = (J * p.nt + I) * p.M + rmu;
+    if (key > pkey) return;
+    const bool self = (key == pkey);
+
+    V *x = static_cast<V *>(p.data);
+    const int col = threadIdx.x % TS;
+    const int r0 = threadIdx.x / TS;
+    // element (row a, col b) of tile A: x[((I*TS + a)*M + mu)*R + J*TS + b]
+    const int64_t rowA = p.M * p.R;  // stride between consecutive outer rows
+    const int64_t baseA = (I * TS * p.M + mu) * p.R + J * TS;
+    const int64_t baseB = (J * TS * p.M + rmu) * p.R + I * TS;
+#pragma unroll
+    for (int a = r0; a < TS; a += ROWS_PER_PASS) ta[a][col] = x[baseA + a * rowA + col];
+    if (!self) {
+#pragma unroll
+        for (int a = r0; a < TS; a += ROWS_PER_PASS) tb[a][col] = x[baseB + a * rowA + col];
+    }
+    __syncthreads();
+    if (self) {
+#pragma unroll
+        for (int a = r0; a < TS; a += ROWS_PER_PASS) x[baseA + a * rowA + col] = ta[col][a];
+    } else {
+#pragma unroll
+        for (int a = r0; a < TS; a += ROWS_PER_PASS) {
+            x[baseB + a * rowA + col] = ta[col][a];
+            x[baseA + a * rowA + col] = tb[col][a];
+        }
+    }
+}
+
+// ----------------------------------------------------------------- tables
+// lo[j] = W_N^j (j < 2^h), hi[j] = W_N^(j*2^h), W_N^m = exp(-2*pi*i*m/N)
+// evaluated in FP64 from the exact ratio 2m/N with sincospi.
+__global__ void twiddle_table_kernel(double2 *lo, int64_t n_lo, double2 *hi, int64_t n_hi, int h,
+                                     int q)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const double inv = ldexp(1.0, 1 - q);  // 2/N, exact
+    if (i < n_lo) {
+        double s, c;
+        sincospi(double(i) * inv, &s, &c);
+        lo[i] = double2{c, -s};
+    }
+    if (i < n_hi) {
+        double s, c;
+        sincospi(ldexp(double(i), h) * inv, &s, &c);
+        hi[i] = double2{c, -s};
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename T, int LOGL, int LINES, int LAYOUT>
+static hipError_t launch_one(const StageParams &p, hipStream_t stream)
+{
+    constexpr int NT = LINES * LineGeom<(1 << LOGL)>::P;
+    hipLaunchKernelGGL((stage_kernel<T, LOGL, LINES, LAYOUT>), dim3(unsigned(p.ntiles)), dim3(NT), 0,
+                       stream, p);
+    return hipGetLastError();
+}
+
+// row layout: workgroups of about 256 threads, or one line when fewer exist
+int row_lines(int dtype_bytes, int logl, int64_t nlines)
+{
+    (void)dtype_bytes;
+    const int p = threads_per_line(logl);
+    int want = p >= 256 ? 1 : 256 / p;
+    return nlines >= want ? want : 1;
+}
+
+template <typename T, int LOGL>
+static hipError_t dispatch_logl(int layout, int lines, const StageParams &p, hipStream_t stream)
+{
+    constexpr int P = LineGeom<(1 << LOGL)>::P;
+    constexpr int ROWW = P >= 256 ? 1 : 256 / P;
+    constexpr int COLW = sizeof(T) == 8 ? 8 : 16;
+    if (layout == LAYOUT_ROW) {
+        if (lines == ROWW) return launch_one<T, LOGL, ROWW, LAYOUT_ROW>(p, stream);
+        if (lines == 1) return launch_one<T, LOGL, 1, LAYOUT_ROW>(p, stream);
+        return hipErrorInvalidValue;
+    }
+    if constexpr (LOGL >= 4 && LOGL <= 10) {
+        if (lines != COLW) return hipErrorInvalidValue;
+        if (layout == LAYOUT_COL) return launch_one<T, LOGL, COLW, LAYOUT_COL>(p, stream);
+        if (layout == LAYOUT_COL2ROW) return launch_one<T, LOGL, COLW, LAYOUT_COL2ROW>(p, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t dispatch_type(int layout, int logl, int lines, const StageParams &p,
+                                hipStream_t stream)
+{
+    switch (logl) {
+    case 0: return dispatch_logl<T, 0>(layout, lines, p, stream);
+    case 1: return dispatch_logl<T, 1>(layout, lines, p, stream);
+    case 2: return dispatch_logl<T, 2>(layout, lines, p, stream);
+    case 3: return dispatch_logl<T, 3>(layout, lines, p, stream);
+    case 4: return dispatch_logl<T, 4>(layout, lines, p, stream);
+    case 5: return dispatch_logl<T, 5>(layout, lines, p, stream);
+    case 6: return dispatch_logl<T, 6>(layout, lines, p, stream);
+    case 7: return dispatch_logl<T, 7>(layout, lines, p, stream);
+    case 8: return dispatch_logl<T, 8>(layout, lines, p, stream);
+    case 9: return dispatch_logl<T, 9>(layout, lines, p, stream);
+    case 10: return dispatch_logl<T, 10>(layout, lines, p, stream);
+    case 11: return dispatch_logl<T, 11>(layout, lines, p, stream);
+    case 12: return dispatch_logl<T, 12>(layout, lines, p, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stage(int dtype_bytes, int layout, int logl, int lines, const StageParams &p,
+                        hipStream_t stream)
+{
+    if (dtype_bytes == 16) return dispatch_type<double>(layout, logl, lines, p, stream);
+    if (dtype_bytes == 8) return dispatch_type<float>(layout, logl, lines, p, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_swap(int dtype_bytes, const SwapParams &p, hipStream_t stream)
+{
+    const int64_t ts = p.R / p.nt;
+    if (p.M > (int64_t(1) << 24) || p.nt * p.nt > 65535) return hipErrorInvalidValue;
+    const dim3 grid(unsigned(p.M), unsigned(p.nt * p.nt));
+#define EFFT_SWAP(T, TSV)                                                             \
+    if (ts == TSV) {                                                                  \
+        hipLaunchKernelGGL((swap_kernel<T, TSV>), grid, dim3(256), 0, stream, p);     \
+        return hipGetLastError();                                                     \
+    }
+    if (dtype_bytes == 16) {
+        EFFT_SWAP(double, 32)
+        EFFT_SWAP(double, 16)
+        EFFT_SWAP(double, 8)
+        EFFT_SWAP(double, 4)
+        EFFT_SWAP(double, 2)
+    } else if (dtype_bytes == 8) {
+        EFFT_SWAP(float, 32)
+        EFFT_SWAP(float, 16)
+        EFFT_SWAP(float, 8)
+        EFFT_SWAP(float, 4)
+        EFFT_SWAP(float, 2)
+    }
+#undef EFFT_SWAP
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_twiddle_table(double2 *lo, int64_t n_lo, double2 *hi, int64_t n_hi, int h, int q,
+                                hipStream_t stream)
+{
+    const int64_t n = n_lo > n_hi ? n_lo : n_hi;
+    const unsigned grid = unsigned((n + 255) / 256);
+    hipLaunchKernelGGL(twiddle_table_kernel, dim3(grid), dim3(256), 0, stream, lo, n_lo, hi, n_hi, h, q);
+    return hipGetLastError();
+}
+
+}  // namespace efft
