@@ -147,7 +147,9 @@ int efft_plan_passes(const efft_plan_t *plan);
  * transformed first) into log2_radix[0 .. m), at most max_digits of them, and
  * returns m, or a negative status for invalid arguments.  *passes receives the
  * number of kernel launches (m sub-FFT passes, plus one digit-reversal pass
- * for in-place plans with m >= 2).
+ * for in-place plans with m >= 2).  It also checks, without launching
+ * anything, that the library holds a kernel for every pass of that plan, and
+ * returns EFFT_ERR_SIZE if not.
  */
 int efft_schedule(int64_t n, int dtype, int inplace, int *log2_radix, int max_digits,
                   int *passes);

@@ -37,7 +37,7 @@ constexpr int MAX_DIGITS = 6;
 
 struct Pass {
     bool swap;
-    int layout, logl, lines;
+    int layout, logl, lines, sets;
     StageParams sp;  // src/dst filled at exec time
     SwapParams wp;   // data filled at exec time
 };
@@ -202,16 +202,18 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
             ps.sp.s = s;
             ps.sp.B = s * L;
             ps.sp.n_over_l = uint64_t(n / L);
+            ps.sets = 1;
             if (s == 1) {
                 ps.layout = LAYOUT_ROW;
                 ps.lines = row_lines(p->eb, d[j], n / L);
             } else {
                 ps.layout = LAYOUT_COL;
-                ps.lines = col_lines(p->eb);
+                ps.lines = col_lines(p->eb, d[j], s, true);
+                ps.sets = col_sets(p->eb, d[j], ps.lines, s);
                 ps.sp.twmode = TW_OFFSET;
                 ps.sp.tw_scale = uint64_t(n / (s * L));
             }
-            ps.sp.ntiles = (n / L) / ps.lines;
+            ps.sp.ntiles = (n / L) / (ps.lines * ps.sets);
             p->passes.push_back(ps);
         }
         if (m >= 2) {
@@ -225,7 +227,7 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
                 M <<= d[i];
             }
             ps.wp.M = M;
-            const int64_t ts = ps.wp.R < 32 ? ps.wp.R : 32;
+            const int64_t ts = swap_tile(p->eb, ps.wp.R);
             ps.wp.nt = ps.wp.R / ts;
             p->passes.push_back(ps);
         }
@@ -238,6 +240,7 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
         ps.logl = d[0];
         ps.layout = LAYOUT_ROW;
         ps.lines = row_lines(p->eb, d[0], 1);
+        ps.sets = 1;
         ps.sp = base_params(p, tt);
         ps.sp.s = 1;
         ps.sp.B = n;
@@ -251,7 +254,8 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
         ps.swap = false;
         ps.logl = d[0];
         ps.layout = LAYOUT_COL2ROW;
-        ps.lines = col_lines(p->eb);
+        ps.lines = col_lines(p->eb, d[0], n >> d[0], false);
+        ps.sets = 1;
         const int64_t L = int64_t(1) << d[0];
         ps.sp = base_params(p, tt);
         ps.sp.s = n / L;
@@ -270,7 +274,8 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
         ps.swap = false;
         ps.logl = d[j];
         ps.layout = LAYOUT_COL;
-        ps.lines = col_lines(p->eb);
+        ps.lines = col_lines(p->eb, d[j], C, true);
+        ps.sets = col_sets(p->eb, d[j], ps.lines, C);
         const int64_t L = int64_t(1) << d[j];
         ps.sp = base_params(p, tt);
         ps.sp.s = C;
@@ -282,7 +287,7 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
             ps.sp.rev.nd = 0;
             for (int i = j + 1; i < m; ++i) ps.sp.rev.bits[ps.sp.rev.nd++] = d[i];  // H = n_{j+1} + ...
         }
-        ps.sp.ntiles = (n / L) / ps.lines;
+        ps.sp.ntiles = (n / L) / (ps.lines * ps.sets);
         p->passes.push_back(ps);
         C *= L;
     }
@@ -311,7 +316,7 @@ int run(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, voi
             // the first pass reads the input; every later pass works in place on out
             ps.sp.src = (i == 0) ? in : out;
             ps.sp.dst = out;
-            e = launch_stage(p->eb, ps.layout, ps.logl, ps.lines, ps.sp, stream);
+            e = launch_stage(p->eb, ps.layout, ps.logl, ps.lines, ps.sets, ps.sp, stream);
         }
         if (e != hipSuccess) return EFFT_ERR_HIP;
     }
@@ -501,13 +506,34 @@ int efft_schedule(int64_t n, int dtype, int inplace, int *log2_radix, int max_di
     const int eb = dtype_bytes(dtype);
     if (!eb) return EFFT_ERR_DTYPE;
     if (!log2_radix || !passes) return EFFT_ERR_NULLPTR;
-    int d[MAX_DIGITS];
-    const int m = plan_digits(q, eb, inplace ? 1 : 0, d);
-    if (m < 1) return EFFT_ERR_SIZE;
-    if (m > max_digits) return EFFT_ERR_ARG;
-    for (int i = 0; i < m; ++i) log2_radix[i] = d[i];
-    *passes = m + ((inplace && m >= 2) ? 1 : 0);
-    return m;
+    // build the plan's passes without device tables and check that a kernel
+    // instantiation exists for each of them
+    efft_plan_s probe{};
+    probe.magic = PLAN_MAGIC;
+    probe.n = n;
+    probe.q = q;
+    probe.dtype = dtype;
+    probe.dir = EFFT_FORWARD;
+    probe.inplace = inplace ? 1 : 0;
+    probe.eb = eb;
+    probe.scale = 1.0;
+    probe.m = plan_digits(q, eb, probe.inplace, probe.digits);
+    if (probe.m < 1) return EFFT_ERR_SIZE;
+    if (probe.m > max_digits) return EFFT_ERR_ARG;
+    TwTable tt{};
+    build_passes(&probe, tt);
+    set_dry_run(true);
+    int status = EFFT_OK;
+    for (const Pass &ps : probe.passes) {
+        const hipError_t e = ps.swap ? launch_swap(eb, ps.wp, nullptr)
+                                     : launch_stage(eb, ps.layout, ps.logl, ps.lines, ps.sets, ps.sp, nullptr);
+        if (e != hipSuccess) status = EFFT_ERR_SIZE;
+    }
+    set_dry_run(false);
+    if (status != EFFT_OK) return status;
+    for (int i = 0; i < probe.m; ++i) log2_radix[i] = probe.digits[i];
+    *passes = int(probe.passes.size());
+    return probe.m;
 }
 
 }  // extern "C"

@@ -70,15 +70,78 @@ struct SwapParams {
     Digits mid;    // middle digits, lowest first
 };
 
+// Tile edge of the digit-reversal swap: 64 x 64 tiles (512-byte runs for
+// complex64, 1 KiB for complex128) when the outer digit allows; measured
+// 1.2x faster than 32 x 32 for complex128 at N = 2^30.
+#ifndef EFFT_SWAP_TS16
+#define EFFT_SWAP_TS16 64
+#endif
+#ifndef EFFT_SWAP_TS8
+#define EFFT_SWAP_TS8 64
+#endif
+inline int64_t swap_tile(int dtype_bytes, int64_t R)
+{
+    const int64_t ts = dtype_bytes == 16 ? EFFT_SWAP_TS16 : EFFT_SWAP_TS8;
+    return R < ts ? R : ts;
+}
+
 // kernel launchers (efft_kernels.hip); return hipSuccess or the launch error
-hipError_t launch_stage(int dtype_bytes, int layout, int logl, int lines, const StageParams &p,
-                        hipStream_t stream);
+hipError_t launch_stage(int dtype_bytes, int layout, int logl, int lines, int sets,
+                        const StageParams &p, hipStream_t stream);
 hipError_t launch_swap(int dtype_bytes, const SwapParams &p, hipStream_t stream);
 hipError_t launch_twiddle_table(double2 *lo, int64_t n_lo, double2 *hi, int64_t n_hi, int h,
                                 int q, hipStream_t stream);
+// while on (per host thread), launch_stage / launch_swap only check that a
+// kernel exists for the arguments and launch nothing
+void set_dry_run(bool on);
 
-// lines per workgroup of the column layouts: one 128-byte row segment
-inline int col_lines(int dtype_bytes) { return dtype_bytes == 16 ? 8 : 16; }
+// LDS budget of one workgroup tile (one workgroup per CU on gfx950's 160 KB)
+constexpr int TILE_LDS_BYTES = 143360;
+
+// Lines per workgroup set of the strided layouts when the tile is made as
+// wide as the LDS budget and 1024 threads allow: each tile row is then one
+// long contiguous run.  Shorter lines get wider tiles.
+__host__ __device__ constexpr int col_lines_max(int dtype_bytes, int logl)
+{
+    const int l = 1 << logl;
+    const int p = logl >= 4 ? l / 16 : 1;
+    const int padded = l + (l >> 4) + 2;
+    int w = 1024 / p;
+    while (w > 1 && w * padded * dtype_bytes > TILE_LDS_BYTES) w >>= 1;
+    if (w > 256) w = 256;
+    return w;
+}
+// the narrow tile: one 128-byte segment per row
+__host__ __device__ constexpr int col_lines_min(int dtype_bytes) { return dtype_bytes == 16 ? 8 : 16; }
+
+// Measured on gfx950: a pass that reads and writes the same strided lines
+// gains from long tile rows only at large strides (at a 2^24-element stride
+// 512-byte rows ran 1.7x faster than 128-byte rows), while at small strides
+// and for passes that write contiguous rows the narrow tile wins, because its
+// smaller LDS footprint lets several workgroups share a CU.
+constexpr int64_t WIDE_TILE_STRIDE = int64_t(1) << 17;
+
+inline int col_lines(int dtype_bytes, int logl, int64_t stride, bool same_positions)
+{
+    const int w = col_lines_max(dtype_bytes, logl);
+    if (same_positions && stride >= WIDE_TILE_STRIDE && stride >= w) return w;
+    return col_lines_min(dtype_bytes);
+}
+
+// Line sets per workgroup of LAYOUT_COL passes: where even the widest tile is
+// a single 128-byte segment (complex128 lines of 1024 points), a second set
+// loaded together makes each tile row a 256-byte run at large strides; the
+// register file has room for it with 512 threads.
+#ifndef EFFT_COL_SETS
+#define EFFT_COL_SETS 2
+#endif
+inline int col_sets(int dtype_bytes, int logl, int lines, int64_t stride)
+{
+    return (EFFT_COL_SETS >= 2 && dtype_bytes == 16 && col_lines_max(dtype_bytes, logl) == 8 &&
+            lines == 8 && stride >= (int64_t(1) << 16))
+               ? 2
+               : 1;
+}
 
 // lines per workgroup of the row layout for a given line length
 int row_lines(int dtype_bytes, int logl, int64_t nlines);

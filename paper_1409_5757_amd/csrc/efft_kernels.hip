@@ -16,6 +16,10 @@
 
 #include "efft_internal.hpp"
 
+#ifndef EFFT_XCD_REMAP
+#define EFFT_XCD_REMAP 1
+#endif
+
 namespace efft {
 
 // LDS index of point p of a line: one padding slot per 16 points breaks the
@@ -47,6 +51,34 @@ template <int LOGL> struct Radices {
     }
 };
 
+// u[r] *= w^r for 0 < r < R, with w^r = w^(4a) * w^b formed from
+// w, w^2, w^3, w^4, w^8, w^12 in FP64 (at most four roundings each) and
+// rounded once to the storage type.
+template <typename V, int R>
+__device__ __forceinline__ void twiddle_line(V *u, double2 w)
+{
+    if constexpr (R == 2) {
+        u[1] = cmul(u[1], round_tw<V>(w));
+    } else {
+        const double2 w2 = cmul(w, w);
+        const double2 w3 = cmul(w2, w);
+        u[1] = cmul(u[1], round_tw<V>(w));
+        u[2] = cmul(u[2], round_tw<V>(w2));
+        u[3] = cmul(u[3], round_tw<V>(w3));
+        if constexpr (R > 4) {
+            const double2 w4 = cmul(w2, w2);
+#pragma unroll
+            for (int a = 1; a < R / 4; ++a) {
+                const double2 c = a == 1 ? w4 : a == 2 ? cmul(w4, w4) : cmul(cmul(w4, w4), w4);
+                u[4 * a] = cmul(u[4 * a], round_tw<V>(c));
+                u[4 * a + 1] = cmul(u[4 * a + 1], round_tw<V>(cmul(c, w)));
+                u[4 * a + 2] = cmul(u[4 * a + 2], round_tw<V>(cmul(c, w2)));
+                u[4 * a + 3] = cmul(u[4 * a + 3], round_tw<V>(cmul(c, w3)));
+            }
+        }
+    }
+}
+
 // One Stockham step on the thread's E registers.  Butterfly j = t + P*b
 // (b < E/R) takes points j + (L/R)*r, i.e. registers b + (E/R)*r; after the
 // twiddle W_{NS*R}^{(j mod NS)*r} and an R-point DFT, output r goes to line
@@ -69,10 +101,7 @@ __device__ __forceinline__ void stockham_step(V *v, V *lds_line, int t, const Tw
             const int jm = j & (NS - 1);
             // W_{NS*R}^{jm} = W_N^{jm * N/(NS*R)}
             const uint64_t m = uint64_t(jm) * (n_over_l * uint64_t(L / (NS * R)));
-            double2 p[R];
-            powers<R>(tw_lookup(tt, m), p);
-#pragma unroll
-            for (int r = 1; r < R; ++r) u[r] = cmul(u[r], round_tw<V>(p[r]));
+            twiddle_line<V, R>(u, tw_lookup(tt, m));
         }
         dft<R>(u);
         if constexpr (TO_LDS) {
@@ -138,18 +167,35 @@ __device__ __forceinline__ void line_fft(V *v, V *lds_line, int t, const TwTable
 }
 
 // Multiply v[i] (output k = t + P*i of a line) by W_N^(g*k*scale): two table
-// lookups and a power ladder in FP64, rounded once to the storage type.
+// lookups, then W^(g*scale*(t + P*(4a + b))) = c_a * s^b with c_a = w0 * s^(4a),
+// s = W^(g*scale*P), all in FP64 and rounded once to the storage type.
 template <typename V, int E, int P>
 __device__ __forceinline__ void apply_stage_twiddle(V *v, int t, uint64_t g, uint64_t scale,
                                                     const TwTable &tt)
 {
     const uint64_t gs = g * scale;
     const double2 w0 = tw_lookup(tt, gs * uint64_t(t));
-    const double2 ws = tw_lookup(tt, gs * uint64_t(P));
-    double2 p[E];
-    powers<E>(ws, p);
+    const double2 s1 = tw_lookup(tt, gs * uint64_t(P));
+    if constexpr (E == 1) {
+        v[0] = cmul(v[0], round_tw<V>(w0));
+    } else {
+        const double2 s2 = cmul(s1, s1);
+        const double2 s3 = cmul(s2, s1);
+        const double2 s4 = cmul(s2, s2);
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = cmul(v[i], round_tw<V>(cmul(w0, p[i])));
+        for (int a = 0; a < (E + 3) / 4; ++a) {
+            double2 c = w0;
+            if (a == 1) c = cmul(w0, s4);
+            if (a == 2) c = cmul(w0, cmul(s4, s4));
+            if (a == 3) c = cmul(cmul(w0, s4), cmul(s4, s4));
+#pragma unroll
+            for (int b = 0; b < 4 && 4 * a + b < E; ++b) {
+                const int i = 4 * a + b;
+                const double2 w = b == 0 ? c : b == 1 ? cmul(c, s1) : b == 2 ? cmul(c, s2) : cmul(c, s3);
+                v[i] = cmul(v[i], round_tw<V>(w));
+            }
+        }
+    }
 }
 
 // Output scaling (last pass only) and the conjugation of the backward direction.
@@ -168,7 +214,23 @@ __device__ __forceinline__ void finish_outputs(V *v, const StageParams &sp)
     }
 }
 
-template <typename T, int LOGL, int LINES, int LAYOUT>
+// Workgroup -> tile order.  The hardware deals consecutive workgroups round
+// robin to the 8 XCDs; handing each XCD one contiguous run of tiles instead
+// keeps neighbouring tiles (adjacent 128-byte row segments) in flight on the
+// same XCD at the same time.
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t ntiles)
+{
+#if EFFT_XCD_REMAP
+    if ((ntiles & 7) == 0) return (bid & 7) * (ntiles >> 3) + (bid >> 3);
+#endif
+    return bid;
+}
+
+// One pass: each workgroup transforms LINES * SETS lines.  Thread (c, t)
+// owns points t + P*i of lines c + LINES*set (set < SETS): the SETS line sets
+// are loaded together, so a strided tile row is one LINES*SETS-element run,
+// and then transformed one set at a time through the same LDS buffer.
+template <typename T, int LOGL, int LINES, int SETS, int LAYOUT>
 __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
     stage_kernel(StageParams sp)
 {
@@ -178,6 +240,7 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
     constexpr int P = LineGeom<L>::P;
     constexpr int PADDED = LineGeom<L>::PADDED;
     constexpr bool NEED_LDS = (Radices<LOGL>::NSTEPS > 1) || (LAYOUT == LAYOUT_COL2ROW);
+    static_assert(LAYOUT != LAYOUT_COL2ROW || SETS == 1, "one line set for row writes");
     __shared__ V lds[NEED_LDS ? LINES * PADDED : 1];
 
     const int tid = threadIdx.x;
@@ -189,47 +252,64 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
         c = tid % LINES;
         t = tid / LINES;
     }
-    const int64_t line = int64_t(blockIdx.x) * LINES + c;
-    const int64_t blk = line / sp.s;
-    const int64_t o = line - blk * sp.s;
-    const int64_t base = blk * sp.B + o;
+    const int64_t tile = xcd_tile(blockIdx.x, sp.ntiles);
     const V *src = static_cast<const V *>(sp.src);
     V *dst = static_cast<V *>(sp.dst);
 
-    V v[E];
+    int64_t base[SETS], off[SETS], blkv[SETS];
+    V v[SETS][E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = src[base + sp.s * int64_t(t + P * i)];
+    for (int st = 0; st < SETS; ++st) {
+        const int64_t line = tile * (LINES * SETS) + st * LINES + c;
+        blkv[st] = line / sp.s;
+        off[st] = line - blkv[st] * sp.s;
+        base[st] = blkv[st] * sp.B + off[st];
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+#pragma unroll
+        for (int st = 0; st < SETS; ++st) v[st][i] = src[base[st] + sp.s * int64_t(t + P * i)];
+    }
     if (sp.conj) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) v[i].y = -v[i].y;
+        for (int st = 0; st < SETS; ++st) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[st][i].y = -v[st][i].y;
+        }
     }
 
     V *lds_line = lds + (NEED_LDS ? c * PADDED : 0);
     if constexpr (LAYOUT != LAYOUT_COL2ROW) {
-        line_fft<V, LOGL, false>(v, lds_line, t, sp.tt, sp.n_over_l);
-        if (sp.twmode != TW_NONE) {
-            const uint64_t g = sp.twmode == TW_OFFSET ? uint64_t(o) : digit_reverse(uint64_t(blk), sp.rev);
-            apply_stage_twiddle<V, E, P>(v, t, g, sp.tw_scale, sp.tt);
-        }
-        finish_outputs<V, E>(v, sp);
 #pragma unroll
-        for (int i = 0; i < E; ++i) dst[base + sp.s * int64_t(t + P * i)] = v[i];
+        for (int st = 0; st < SETS; ++st) {
+            if (st > 0) __syncthreads();  // the previous set has finished with LDS
+            line_fft<V, LOGL, false>(v[st], lds_line, t, sp.tt, sp.n_over_l);
+            if (sp.twmode != TW_NONE) {
+                const uint64_t g = sp.twmode == TW_OFFSET ? uint64_t(off[st])
+                                                          : digit_reverse(uint64_t(blkv[st]), sp.rev);
+                apply_stage_twiddle<V, E, P>(v[st], t, g, sp.tw_scale, sp.tt);
+            }
+            finish_outputs<V, E>(v[st], sp);
+#pragma unroll
+            for (int i = 0; i < E; ++i) dst[base[st] + sp.s * int64_t(t + P * i)] = v[st][i];
+        }
     } else {
         // outputs land in LDS in natural order; re-read them one contiguous
         // row per line and write that row at its digit-reversed position
-        line_fft<V, LOGL, true>(v, lds_line, t, sp.tt, sp.n_over_l);
+        line_fft<V, LOGL, true>(v[0], lds_line, t, sp.tt, sp.n_over_l);
         __syncthreads();
         const int t2 = tid % P;
         const int c2 = tid / P;
-        const int64_t o2 = int64_t(blockIdx.x) * LINES + c2;  // one block: line == offset
+        const int64_t o2 = tile * LINES + c2;  // one block: line == offset
         const V *row_lds = lds + c2 * PADDED;
+        V w[E];
 #pragma unroll
-        for (int i = 0; i < E; ++i) v[i] = row_lds[lds_pad(t2 + P * i)];
-        apply_stage_twiddle<V, E, P>(v, t2, uint64_t(o2), sp.tw_scale, sp.tt);
-        finish_outputs<V, E>(v, sp);
+        for (int i = 0; i < E; ++i) w[i] = row_lds[lds_pad(t2 + P * i)];
+        apply_stage_twiddle<V, E, P>(w, t2, uint64_t(o2), sp.tw_scale, sp.tt);
+        finish_outputs<V, E>(w, sp);
         const int64_t row = sp.row_mul * int64_t(digit_reverse(uint64_t(o2), sp.rev));
 #pragma unroll
-        for (int i = 0; i < E; ++i) dst[row + t2 + P * i] = v[i];
+        for (int i = 0; i < E; ++i) dst[row + t2 + P * i] = w[i];
     }
 }
 
@@ -239,17 +319,16 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
 // Each unordered pair is handled by the workgroup whose key is the smaller;
 // a tile paired with itself is transposed in place.  Every element is read
 // and written exactly once.
-template <typename T, int TS>
-__global__ void __launch_bounds__(256) swap_kernel(SwapParams p)
+template <typename T, int TS, int NT>
+__global__ void __launch_bounds__(NT) swap_kernel(SwapParams p)
 {
     using V = typename vec2<T>::type;
-    constexpr int NT = 256;
     constexpr int ROWS_PER_PASS = NT / TS;
     __shared__ V ta[TS][TS + 1];
     __shared__ V tb[TS][TS + 1];
 
     // grid: x = middle index mu (up to 2^24), y = tile pair I*nt + J (up to 1024)
-    const int64_t mu = blockIdx.x;
+    const int64_t mu = xcd_tile(blockIdx.x, p.M);
     const int64_t ij = blockIdx.y;
     const int64_t I = ij / p.nt;
     const int64_t J = ij - I * p.nt;
@@ -306,12 +385,17 @@ __global__ void twiddle_table_kernel(double2 *lo, int64_t n_lo, double2 *hi, int
 }
 
 // ---------------------------------------------------------------- launchers
-template <typename T, int LOGL, int LINES, int LAYOUT>
+// Set while a host-only caller checks that a kernel exists for every pass of
+// a plan: the launchers then return success without launching anything.
+thread_local bool g_dry_run = false;
+
+template <typename T, int LOGL, int LINES, int SETS, int LAYOUT>
 static hipError_t launch_one(const StageParams &p, hipStream_t stream)
 {
     constexpr int NT = LINES * LineGeom<(1 << LOGL)>::P;
-    hipLaunchKernelGGL((stage_kernel<T, LOGL, LINES, LAYOUT>), dim3(unsigned(p.ntiles)), dim3(NT), 0,
-                       stream, p);
+    if (g_dry_run) return hipSuccess;
+    hipLaunchKernelGGL((stage_kernel<T, LOGL, LINES, SETS, LAYOUT>), dim3(unsigned(p.ntiles)), dim3(NT),
+                       0, stream, p);
     return hipGetLastError();
 }
 
@@ -325,51 +409,66 @@ int row_lines(int dtype_bytes, int logl, int64_t nlines)
 }
 
 template <typename T, int LOGL>
-static hipError_t dispatch_logl(int layout, int lines, const StageParams &p, hipStream_t stream)
+static hipError_t dispatch_logl(int layout, int lines, int sets, const StageParams &p,
+                                hipStream_t stream)
 {
     constexpr int P = LineGeom<(1 << LOGL)>::P;
     constexpr int ROWW = P >= 256 ? 1 : 256 / P;
-    constexpr int COLW = sizeof(T) == 8 ? 8 : 16;
+    constexpr int WMAX = col_lines_max(int(2 * sizeof(T)), LOGL);
+    constexpr int WMIN = col_lines_min(int(2 * sizeof(T)));
     if (layout == LAYOUT_ROW) {
-        if (lines == ROWW) return launch_one<T, LOGL, ROWW, LAYOUT_ROW>(p, stream);
-        if (lines == 1) return launch_one<T, LOGL, 1, LAYOUT_ROW>(p, stream);
+        if (sets != 1) return hipErrorInvalidValue;
+        if (lines == ROWW) return launch_one<T, LOGL, ROWW, 1, LAYOUT_ROW>(p, stream);
+        if (lines == 1) return launch_one<T, LOGL, 1, 1, LAYOUT_ROW>(p, stream);
         return hipErrorInvalidValue;
     }
     if constexpr (LOGL >= 4 && LOGL <= 10) {
-        if (lines != COLW) return hipErrorInvalidValue;
-        if (layout == LAYOUT_COL) return launch_one<T, LOGL, COLW, LAYOUT_COL>(p, stream);
-        if (layout == LAYOUT_COL2ROW) return launch_one<T, LOGL, COLW, LAYOUT_COL2ROW>(p, stream);
+        if (layout == LAYOUT_COL) {
+            if (lines == WMAX && sets == 1) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL>(p, stream);
+            if constexpr (WMAX == 8) {
+                if (lines == WMAX && sets == 2) return launch_one<T, LOGL, WMAX, 2, LAYOUT_COL>(p, stream);
+            }
+            if constexpr (WMIN != WMAX) {
+                if (lines == WMIN && sets == 1) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL>(p, stream);
+            }
+        }
+        if (layout == LAYOUT_COL2ROW && sets == 1) {
+            if (lines == WMAX) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL2ROW>(p, stream);
+            if constexpr (WMIN != WMAX) {
+                if (lines == WMIN) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL2ROW>(p, stream);
+            }
+        }
     }
     return hipErrorInvalidValue;
 }
 
 template <typename T>
-static hipError_t dispatch_type(int layout, int logl, int lines, const StageParams &p,
+static hipError_t dispatch_type(int layout, int logl, int lines, int sets, const StageParams &p,
                                 hipStream_t stream)
 {
     switch (logl) {
-    case 0: return dispatch_logl<T, 0>(layout, lines, p, stream);
-    case 1: return dispatch_logl<T, 1>(layout, lines, p, stream);
-    case 2: return dispatch_logl<T, 2>(layout, lines, p, stream);
-    case 3: return dispatch_logl<T, 3>(layout, lines, p, stream);
-    case 4: return dispatch_logl<T, 4>(layout, lines, p, stream);
-    case 5: return dispatch_logl<T, 5>(layout, lines, p, stream);
-    case 6: return dispatch_logl<T, 6>(layout, lines, p, stream);
-    case 7: return dispatch_logl<T, 7>(layout, lines, p, stream);
-    case 8: return dispatch_logl<T, 8>(layout, lines, p, stream);
-    case 9: return dispatch_logl<T, 9>(layout, lines, p, stream);
-    case 10: return dispatch_logl<T, 10>(layout, lines, p, stream);
-    case 11: return dispatch_logl<T, 11>(layout, lines, p, stream);
-    case 12: return dispatch_logl<T, 12>(layout, lines, p, stream);
+    case 0: return dispatch_logl<T, 0>(layout, lines, sets, p, stream);
+    case 1: return dispatch_logl<T, 1>(layout, lines, sets, p, stream);
+    case 2: return dispatch_logl<T, 2>(layout, lines, sets, p, stream);
+    case 3: return dispatch_logl<T, 3>(layout, lines, sets, p, stream);
+    case 4: return dispatch_logl<T, 4>(layout, lines, sets, p, stream);
+    case 5: return dispatch_logl<T, 5>(layout, lines, sets, p, stream);
+    case 6: return dispatch_logl<T, 6>(layout, lines, sets, p, stream);
+    case 7: return dispatch_logl<T, 7>(layout, lines, sets, p, stream);
+    case 8: return dispatch_logl<T, 8>(layout, lines, sets, p, stream);
+    case 9: return dispatch_logl<T, 9>(layout, lines, sets, p, stream);
+    case 10: return dispatch_logl<T, 10>(layout, lines, sets, p, stream);
+    case 11: return dispatch_logl<T, 11>(layout, lines, sets, p, stream);
+    case 12: return dispatch_logl<T, 12>(layout, lines, sets, p, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_stage(int dtype_bytes, int layout, int logl, int lines, const StageParams &p,
-                        hipStream_t stream)
+hipError_t launch_stage(int dtype_bytes, int layout, int logl, int lines, int sets,
+                        const StageParams &p, hipStream_t stream)
 {
-    if (dtype_bytes == 16) return dispatch_type<double>(layout, logl, lines, p, stream);
-    if (dtype_bytes == 8) return dispatch_type<float>(layout, logl, lines, p, stream);
+    if (dtype_bytes == 16) return dispatch_type<double>(layout, logl, lines, sets, p, stream);
+    if (dtype_bytes == 8) return dispatch_type<float>(layout, logl, lines, sets, p, stream);
     return hipErrorInvalidValue;
 }
 
@@ -378,27 +477,26 @@ hipError_t launch_swap(int dtype_bytes, const SwapParams &p, hipStream_t stream)
     const int64_t ts = p.R / p.nt;
     if (p.M > (int64_t(1) << 24) || p.nt * p.nt > 65535) return hipErrorInvalidValue;
     const dim3 grid(unsigned(p.M), unsigned(p.nt * p.nt));
-#define EFFT_SWAP(T, TSV)                                                             \
+#define EFFT_SWAP(T, TSV, NTV)                                                        \
     if (ts == TSV) {                                                                  \
-        hipLaunchKernelGGL((swap_kernel<T, TSV>), grid, dim3(256), 0, stream, p);     \
+        if (g_dry_run) return hipSuccess;                                             \
+        hipLaunchKernelGGL((swap_kernel<T, TSV, NTV>), grid, dim3(NTV), 0, stream, p); \
         return hipGetLastError();                                                     \
     }
     if (dtype_bytes == 16) {
-        EFFT_SWAP(double, 32)
-        EFFT_SWAP(double, 16)
-        EFFT_SWAP(double, 8)
-        EFFT_SWAP(double, 4)
-        EFFT_SWAP(double, 2)
+        EFFT_SWAP(double, 64, 512)
+        EFFT_SWAP(double, 32, 256)
+        EFFT_SWAP(double, 16, 256)
     } else if (dtype_bytes == 8) {
-        EFFT_SWAP(float, 32)
-        EFFT_SWAP(float, 16)
-        EFFT_SWAP(float, 8)
-        EFFT_SWAP(float, 4)
-        EFFT_SWAP(float, 2)
+        EFFT_SWAP(float, 64, 512)
+        EFFT_SWAP(float, 32, 256)
+        EFFT_SWAP(float, 16, 256)
     }
 #undef EFFT_SWAP
     return hipErrorInvalidValue;
 }
+
+void set_dry_run(bool on) { g_dry_run = on; }
 
 hipError_t launch_twiddle_table(double2 *lo, int64_t n_lo, double2 *hi, int64_t n_hi, int h, int q,
                                 hipStream_t stream)
