@@ -231,3 +231,51 @@ def fill_from_host(out, family: str, seed: int, chunk: int = 1 << 24, **kw) -> N
         else:
             v = generate(family, seed, m, dtype=np_dtype, offset=s, **kw)
         out[s:s + m].copy_(torch.from_numpy(v), non_blocking=False)
+
+
+def fill_normal_torch(out, seed: int, offset: int = 0, chunk: int = 1 << 25) -> None:
+    """Fill a 1D complex torch tensor with i.i.d. standard normal re, im by the
+    same Box-Muller recipe as ``generate('normal', ...)`` applied to the same
+    counter-based uniforms (bit-identical uniforms; the transcendental
+    functions of the device may round differently from the host's)."""
+    import torch
+    key = family_key(seed, "normal")
+    n = out.shape[0]
+    real_dtype = torch.float64 if out.dtype == torch.complex128 else torch.float32
+    view = torch.view_as_real(out)
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        u = unit_doubles_torch(key, 2 * (offset + s), 2 * m, out.device).view(m, 2)
+        r = torch.sqrt(-2.0 * torch.log(1.0 - u[:, 0]))
+        ang = (2.0 * np.pi) * u[:, 1]
+        view[s:s + m, 0].copy_((r * torch.cos(ang)).to(real_dtype))
+        view[s:s + m, 1].copy_((r * torch.sin(ang)).to(real_dtype))
+        del u, r, ang
+
+
+def fill_tones_torch(out, seed: int, count: int = 8, chunk: int = 1 << 25) -> None:
+    """Fill a 1D complex torch tensor of length N with the sum-of-tones signal
+    of ``tone_params(seed, N, count)``, synthesised on the tensor's device in
+    FP64 with the phase index (f*n) mod N reduced exactly in integers."""
+    import torch
+    n = out.shape[0]
+    freqs, phases = tone_params(seed, n, count)
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        idx = torch.arange(s, s + m, dtype=torch.int64, device=out.device)
+        acc = torch.zeros(m, dtype=torch.complex128, device=out.device)
+        for f, ph in zip(freqs.tolist(), phases.tolist()):
+            k = torch.bitwise_and(idx * int(f), n - 1).to(torch.float64)
+            ang = k * (2.0 * np.pi / n) + ph
+            acc += torch.complex(torch.cos(ang), torch.sin(ang))
+        out[s:s + m].copy_(acc.to(out.dtype))
+        del idx, acc
+
+
+def fill_weights_torch(out, seed: int, offset: int = 0, chunk: int = 1 << 25) -> None:
+    """Fill a 1D real torch tensor with ``real_weights(seed, ...)`` (U[0, 1))."""
+    key = family_key(seed, "weights")
+    n = out.shape[0]
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        out[s:s + m].copy_(unit_doubles_torch(key, offset + s, m, out.device).to(out.dtype))

@@ -40,3 +40,35 @@ def run_library(x_host: np.ndarray, dtype, direction: int, inplace: bool, scale:
     out = p.execute(x)
     torch.cuda.synchronize()
     return out.cpu().numpy(), x.cpu().numpy()
+
+
+def oracle_bins_from_device(x_dev: torch.Tensor, bins, sign: int = -1, chunk: int = 1 << 24):
+    """Eq. "eqf" at `bins` by the CPU oracle, streaming the device input to the
+    host chunk by chunk (the values are exactly those the transform reads)."""
+    import oracle
+    n = x_dev.shape[0]
+    acc = None
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        h = x_dev[s:s + m].cpu().numpy()
+        acc = oracle.dft_bins(h, bins, sign=sign, n=n, offset=s, acc=acc)
+    return oracle.bins_value(acc)
+
+
+def sample_bins(n: int, count: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    fixed = [0, 1, n // 2, n - 1] if n > 1 else [0]
+    return np.unique(np.concatenate([fixed, rng.integers(0, n, count)])).astype(np.int64)
+
+
+def device_rel_l2(a: torch.Tensor, b: torch.Tensor, chunk: int = 1 << 26) -> float:
+    """||a - b|| / ||b|| over two device tensors, accumulated in FP64 by chunks."""
+    num = 0.0
+    den = 0.0
+    for s in range(0, a.shape[0], chunk):
+        d = (a[s:s + chunk].to(torch.complex128) - b[s:s + chunk].to(torch.complex128))
+        num += float(torch.sum(d.real ** 2 + d.imag ** 2))
+        bb = b[s:s + chunk].to(torch.complex128)
+        den += float(torch.sum(bb.real ** 2 + bb.imag ** 2))
+        del d, bb
+    return (num / den) ** 0.5 if den > 0 else num ** 0.5
