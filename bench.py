@@ -75,7 +75,8 @@ def time_transform(plan, x, steps: int, warmup: int):
 
 
 def copy_ceiling(nbytes: int) -> float:
-    """Device-to-device copy bandwidth (read + write) in GB/s."""
+    """Device-to-device copy bandwidth (read + write) in GB/s.  Its kernel is
+    also the calibration of the HBM byte counters (known bytes per launch)."""
     import torch
     n = nbytes // 8
     a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
