@@ -163,6 +163,7 @@ StageParams base_params(const efft_plan_s *p, const TwTable &tt)
     sp.rev.nd = 0;
     sp.scale = 1.0;
     sp.apply_scale = 0;
+    sp.order = TILE_XCD;
     return sp;
 }
 
@@ -210,6 +211,7 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
                 ps.layout = LAYOUT_COL;
                 ps.lines = col_lines(p->eb, d[j], s, true);
                 ps.sets = col_sets(p->eb, d[j], ps.lines, s);
+                ps.sp.order = col_order(s);
                 ps.sp.twmode = TW_OFFSET;
                 ps.sp.tw_scale = uint64_t(n / (s * L));
             }
@@ -263,6 +265,7 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
         ps.sp.n_over_l = uint64_t(n / L);
         ps.sp.tw_scale = 1;
         ps.sp.row_mul = L;
+        ps.sp.order = col_order(n / L);
         ps.sp.rev.nd = 0;
         for (int i = m - 1; i >= 1; --i) ps.sp.rev.bits[ps.sp.rev.nd++] = d[i];  // o = n_m + R_m n_{m-1} + ...
         ps.sp.ntiles = (n / L) / ps.lines;
@@ -276,6 +279,7 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
         ps.layout = LAYOUT_COL;
         ps.lines = col_lines(p->eb, d[j], C, true);
         ps.sets = col_sets(p->eb, d[j], ps.lines, C);
+        ps.sp.order = col_order(C);
         const int64_t L = int64_t(1) << d[j];
         ps.sp = base_params(p, tt);
         ps.sp.s = C;

@@ -16,9 +16,6 @@
 
 #include "efft_internal.hpp"
 
-#ifndef EFFT_XCD_REMAP
-#define EFFT_XCD_REMAP 1
-#endif
 
 namespace efft {
 
@@ -215,14 +212,18 @@ __device__ __forceinline__ void finish_outputs(V *v, const StageParams &sp)
 }
 
 // Workgroup -> tile order.  The hardware deals consecutive workgroups round
-// robin to the 8 XCDs; handing each XCD one contiguous run of tiles instead
-// keeps neighbouring tiles (adjacent 128-byte row segments) in flight on the
-// same XCD at the same time.
-__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t ntiles)
+// robin to the 8 XCDs.  TILE_XCD hands each XCD one contiguous run of tiles,
+// so neighbouring tiles (adjacent row segments) are in flight on one XCD at
+// the same time; TILE_XCD_SCATTER additionally walks each XCD's run with an
+// odd multiplicative stride, which spreads concurrent tiles of a pass whose
+// lines are far apart in memory over more DRAM channels.
+__device__ __forceinline__ int64_t order_tiles(int64_t bid, int64_t ntiles, int mode)
 {
-#if EFFT_XCD_REMAP
-    if ((ntiles & 7) == 0) return (bid & 7) * (ntiles >> 3) + (bid >> 3);
-#endif
+    if (mode == TILE_XCD && (ntiles & 7) == 0) return (bid & 7) * (ntiles >> 3) + (bid >> 3);
+    if (mode == TILE_XCD_SCATTER && (ntiles & 63) == 0) {
+        const int64_t c = ntiles >> 3, k = bid >> 3;  // c is a power of two
+        return (bid & 7) * c + ((k * 1031) & (c - 1));
+    }
     return bid;
 }
 
@@ -252,7 +253,7 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
         c = tid % LINES;
         t = tid / LINES;
     }
-    const int64_t tile = xcd_tile(blockIdx.x, sp.ntiles);
+    const int64_t tile = order_tiles(blockIdx.x, sp.ntiles, sp.order);
     const V *src = static_cast<const V *>(sp.src);
     V *dst = static_cast<V *>(sp.dst);
 
@@ -328,7 +329,7 @@ __global__ void __launch_bounds__(NT) swap_kernel(SwapParams p)
     __shared__ V tb[TS][TS + 1];
 
     // grid: x = middle index mu (up to 2^24), y = tile pair I*nt + J (up to 1024)
-    const int64_t mu = xcd_tile(blockIdx.x, p.M);
+    const int64_t mu = order_tiles(blockIdx.x, p.M, TILE_XCD);
     const int64_t ij = blockIdx.y;
     const int64_t I = ij / p.nt;
     const int64_t J = ij - I * p.nt;
