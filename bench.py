@@ -8,10 +8,10 @@ Reports GFLOP/s = 5 N log2 N / t (the nominal complex-FFT count; the paper's
 Eq. "eqflops" is the real-input half of it), per-pass HBM bandwidth from HIP
 events recorded on the launch stream inside the timed region, the same
 transform in complex64 for the FP32 speedup and its error against the FP64
-path, a device-copy ceiling, and the FP64 CPU oracle timed on a bounded
-sample on the host cores.
+path, the paper's own real-input FP32 transform at the same N, a device-copy
+ceiling, and the FP64 CPU oracle timed on a bounded sample on the host cores.
 
-    python bench.py [--steps K] [--warmup W] [--log2n Q] [--no-fp32] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--log2n Q] [--no-fp32] [--no-real] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -127,6 +127,7 @@ def main() -> int:
     ap.add_argument("--log2n", type=int, default=30)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-real", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one transform on one GPU; runs on more than one GPU are not "
@@ -201,6 +202,30 @@ def main() -> int:
             "passes_detail": [{"pass": i, "ms": round(t, 4), "GBps": round(2 * n * 8 / (t * 1e-3) / 1e9, 1)}
                               for i, t in enumerate(pp32)]}
         del x32
+        torch.cuda.empty_cache()
+
+    if not args.no_real:
+        # the paper's own workload: a real FP32 transform, GFLOP/s by its
+        # real-data count 2.5 N log2 N (Eq. "eqflops")
+        xr = torch.empty(n // 2, dtype=torch.complex64, device=dev)
+        inputs.fill_uniform_torch(xr, seed=0, lo=-0.5, hi=0.5)
+        xr = torch.view_as_real(xr).reshape(n)
+        pr = api.RealPlan(n, torch.float32, -1, 1.0, device=dev)
+        yr = torch.empty(n // 2 + 1, dtype=torch.complex64, device=dev)
+        for _ in range(args.warmup):
+            pr.execute(xr, yr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pr.execute(xr, yr)
+        torch.cuda.synchronize()
+        msr = (time.perf_counter() - t0) / args.steps * 1e3
+        result["real_fp32"] = {"workload": f"forward real-to-complex N=2^{q} float32, out of place",
+                               "value": round(2.5 * n * q / (msr * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+                               "count": "2.5 N log2 N", "ms_per_step": round(msr, 4),
+                               "passes": pr.passes}
+        del xr, yr
+        pr.close()
         torch.cuda.empty_cache()
 
     result["copy_ceiling_GBps"] = round(copy_ceiling(min(8 << 30, n * 16)), 1)

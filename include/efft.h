@@ -99,6 +99,26 @@ efft_plan_t *efft_plan(int64_t n, int dtype, int dir, int inplace);
 efft_plan_t *efft_plan_scaled(int64_t n, int dtype, int dir, int inplace, double scale);
 
 /*
+ * Real-data plan for N = 2^q real samples (1 <= q <= 34), always out of
+ * place, executed with efft_exec_oop.  The paper's EFFT transforms real data
+ * (Section 2.1 "code:dfti", Section 4); this keeps the standard half-spectrum
+ * layout rather than MKL's packed "perm" order:
+ *   dir = EFFT_FORWARD  (real to complex): in = N reals (float for EFFT_C64,
+ *       double for EFFT_C128), out = N/2 + 1 complex bins F_0 .. F_{N/2} of
+ *       Eq. "eqf" (the rest follow from F_{N-k} = conj F_k);
+ *   dir = EFFT_BACKWARD (complex to real): in = N/2 + 1 complex bins taken as
+ *       the half of a Hermitian spectrum (the imaginary parts of F_0 and
+ *       F_{N/2} are ignored), out = N reals of the unnormalised backward
+ *       transform (N * x for in = the forward transform of x).
+ * Every output is multiplied by scale (1/N makes the backward transform the
+ * inverse).  Computed as one N/2-point complex transform plus one pass that
+ * combines bins k and N/2 - k in place (one radix-2 level, Section 2.2, Eqs.
+ * "eqct"/"eqctt"; the pair reassembly of Section 3.4).  Input and output must
+ * not overlap; in is not written.  Returns NULL on failure (efft_last_error).
+ */
+efft_plan_t *efft_plan_real(int64_t n, int dtype, int dir, double scale);
+
+/*
  * In-place transform of data[0 .. N) (device pointer, N elements of the
  * plan's dtype), enqueued on stream.  The in-place path is a sequence of
  * batched sub-FFT passes followed by one tiled digit-reversal pass; it needs
@@ -108,7 +128,8 @@ int efft_exec(const efft_plan_t *plan, void *data, void *stream);
 
 /*
  * Out-of-place transform: reads in[0 .. N), writes out[0 .. N), enqueued on
- * stream.  in is never written (the input is preserved, as the paper's
+ * stream (for real-data plans the array sizes are those of efft_plan_real).
+ * in is never written (the input is preserved, as the paper's
  * EFFT_Transform keeps Data() separate from Result(), Section 4).  The two
  * ranges must not overlap.
  */

@@ -12,12 +12,13 @@ EFFT_C128 = 2
 EFFT_FORWARD = -1
 EFFT_BACKWARD = 1
 
-__all__ = ["fft", "bfft", "ifft", "EfftFFT", "Plan", "get_plan", "schedule",
+__all__ = ["fft", "bfft", "ifft", "rfft", "irfft", "EfftFFT", "Plan", "RealPlan", "get_plan", "schedule",
            "EFFT_C64", "EFFT_C128", "EFFT_FORWARD", "EFFT_BACKWARD"]
 
 
 def __getattr__(name):
-    if name in ("fft", "bfft", "ifft", "EfftFFT", "Plan", "get_plan", "clear_plan_cache"):
+    if name in ("fft", "bfft", "ifft", "rfft", "irfft", "EfftFFT", "Plan", "RealPlan", "get_plan",
+                "get_real_plan", "clear_plan_cache"):
         from . import api
         return getattr(api, name)
     if name in ("schedule", "EfftError", "load", "strerror"):

@@ -39,6 +39,8 @@ def _bind(lib):
     lib.efft_plan.restype = vp
     lib.efft_plan_scaled.argtypes = [i64, ci, ci, ci, ctypes.c_double]
     lib.efft_plan_scaled.restype = vp
+    lib.efft_plan_real.argtypes = [i64, ci, ci, ctypes.c_double]
+    lib.efft_plan_real.restype = vp
     lib.efft_exec.argtypes = [vp, vp, vp]
     lib.efft_exec.restype = ci
     lib.efft_exec_oop.argtypes = [vp, vp, vp, vp]

@@ -5,6 +5,8 @@
 ``bfft(x)``  backward (conjugate-sign) transform, unnormalised: the adjoint.
 ``ifft(x)``  inverse DFT = bfft(x) / N; the 1/N = 2^-q factor is applied
              inside the library's last pass and is exact.
+``rfft(x)``  real input of length N -> bins F_0 .. F_{N/2} (N/2 + 1 complex).
+``irfft(X)`` N/2 + 1 Hermitian bins -> N real samples, scaled by 1/N.
 
 Inputs are complex64 / complex128 CUDA tensors whose last dimension is a
 power of two (N = 2^q, q <= 34).  Leading dimensions are a batch of
@@ -107,6 +109,73 @@ class Plan:
             pass
 
 
+_REAL_OF = {torch.complex64: torch.float32, torch.complex128: torch.float64}
+_COMPLEX_OF = {torch.float32: torch.complex64, torch.float64: torch.complex128}
+
+
+class RealPlan:
+    """Real-data transform of N = 2^q samples (out of place): forward maps N
+    reals to N/2 + 1 bins, backward maps N/2 + 1 Hermitian bins to N reals."""
+
+    def __init__(self, n: int, real_dtype: torch.dtype, direction: int = EFFT_FORWARD,
+                 scale: float = 1.0, device=None):
+        if real_dtype not in _COMPLEX_OF:
+            raise TypeError(f"real dtype must be float32 or float64, got {real_dtype}")
+        self.lib = _lib.load()
+        self.n = int(n)
+        self.real_dtype = real_dtype
+        self.complex_dtype = _COMPLEX_OF[real_dtype]
+        self.direction = int(direction)
+        self.scale = float(scale)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        with torch.cuda.device(self.device):
+            h = self.lib.efft_plan_real(self.n, _DTYPES[self.complex_dtype], self.direction, self.scale)
+        if not h:
+            raise EfftError(self.lib.efft_last_error(), "efft_plan_real")
+        self.handle = ctypes.c_void_p(h)
+        self.passes = self.lib.efft_plan_passes(self.handle)
+
+    def execute(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        fwd = self.direction == EFFT_FORWARD
+        in_dtype, in_len = (self.real_dtype, self.n) if fwd else (self.complex_dtype, self.n // 2 + 1)
+        out_dtype, out_len = (self.complex_dtype, self.n // 2 + 1) if fwd else (self.real_dtype, self.n)
+        if x.dtype != in_dtype or x.shape[-1] != in_len or x.device != self.device or not x.is_contiguous():
+            raise ValueError(f"input must be a contiguous {in_dtype} tensor on {self.device} "
+                             f"with last dimension {in_len}")
+        if out is None:
+            out = torch.empty(*x.shape[:-1], out_len, dtype=out_dtype, device=self.device)
+        if out.dtype != out_dtype or out.shape[-1] != out_len or not out.is_contiguous():
+            raise ValueError(f"output must be a contiguous {out_dtype} tensor with last dimension {out_len}")
+        s = ctypes.c_void_p((stream or torch.cuda.current_stream(self.device)).cuda_stream)
+        rows = x.numel() // in_len
+        istep, ostep = in_len * x.element_size(), out_len * out.element_size()
+        xp, op = x.data_ptr(), out.data_ptr()
+        for r in range(rows):
+            _lib.check(self.lib.efft_exec_oop(self.handle, ctypes.c_void_p(xp + r * istep),
+                                              ctypes.c_void_p(op + r * ostep), s), "efft_exec_oop")
+        return out
+
+    def execute_events(self, x: torch.Tensor, out: torch.Tensor, events, stream=None) -> None:
+        s = ctypes.c_void_p((stream or torch.cuda.current_stream(self.device)).cuda_stream)
+        arr = (ctypes.c_void_p * len(events))(*events)
+        _lib.check(self.lib.efft_exec_events(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr()), s, arr, len(events)),
+                   "efft_exec_events")
+
+    def close(self) -> None:
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.efft_destroy(h)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 _cache: dict = {}
 _cache_lock = threading.Lock()
 
@@ -177,3 +246,31 @@ def ifft(x: torch.Tensor, inplace: bool = False, out: torch.Tensor | None = None
     if not inplace and torch.is_grad_enabled() and x.requires_grad:
         return EfftFFT.apply(x, EFFT_BACKWARD, scale)
     return _transform(x, EFFT_BACKWARD, scale, inplace, out)
+
+
+def get_real_plan(n: int, real_dtype: torch.dtype, direction: int, scale: float,
+                  device: torch.device) -> RealPlan:
+    key = ("real", int(n), real_dtype, int(direction), float(scale), device)
+    with _cache_lock:
+        p = _cache.get(key)
+        if p is None:
+            p = RealPlan(n, real_dtype, direction, scale, device)
+            _cache[key] = p
+        return p
+
+
+def rfft(x: torch.Tensor) -> torch.Tensor:
+    """Forward DFT of real input along the last dimension: bins 0 .. N/2."""
+    if not x.is_cuda:
+        raise ValueError("efft transforms run on the GPU only; got a CPU tensor")
+    return get_real_plan(x.shape[-1], x.dtype, EFFT_FORWARD, 1.0, x.device).execute(x.contiguous())
+
+
+def irfft(x: torch.Tensor, n: int | None = None) -> torch.Tensor:
+    """Inverse of rfft: N/2 + 1 Hermitian bins -> N real samples (scaled 1/N)."""
+    if not x.is_cuda:
+        raise ValueError("efft transforms run on the GPU only; got a CPU tensor")
+    n = 2 * (x.shape[-1] - 1) if n is None else int(n)
+    if x.dtype not in _REAL_OF:
+        raise TypeError(f"dtype must be complex64 or complex128, got {x.dtype}")
+    return get_real_plan(n, _REAL_OF[x.dtype], EFFT_BACKWARD, 1.0 / n, x.device).execute(x.contiguous())

@@ -140,6 +140,8 @@ int dtype_bytes(int dtype) { return dtype == EFFT_C128 ? 16 : dtype == EFFT_C64 
 
 }  // namespace
 
+enum PlanKind { KIND_C2C = 0, KIND_R2C = 1, KIND_C2R = 2 };
+
 struct efft_plan_s {
     uint64_t magic;
     int64_t n;
@@ -150,6 +152,11 @@ struct efft_plan_s {
     double scale;
     double2 *tables;
     int64_t table_bytes;
+    // real-input plans: an N/2-point complex plan plus the pairing pass, which
+    // uses W_N^k from this plan's own table (tt_real)
+    int kind;
+    efft_plan_s *inner;
+    TwTable tt_real;
 };
 
 namespace {
@@ -304,8 +311,41 @@ int validate_ptr(const efft_plan_s *p, const void *ptr)
     return EFFT_OK;
 }
 
+int run_c2c(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events,
+            int nevents);
+
+int total_passes(const efft_plan_s *p)
+{
+    return p->kind == KIND_C2C ? int(p->passes.size()) : int(p->inner->passes.size()) + 1;
+}
+
 int run(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events,
         int nevents)
+{
+    if (p->kind == KIND_C2C) return run_c2c(p, in, out, stream, events, nevents);
+    const int np = total_passes(p);
+    if (events && nevents < np + 1) return EFFT_ERR_ARG;
+    const int64_t h = p->n / 2;
+    if (p->kind == KIND_R2C) {
+        // the N reals are read as N/2 complex points; out[0 .. N/2) receives
+        // their transform, then the pairing pass completes out[0 .. N/2]
+        const int r = run_c2c(p->inner, in, out, stream, events, events ? nevents - 1 : 0);
+        if (r != EFFT_OK) return r;
+        if (launch_r2c_post(p->eb, out, h, p->tt_real, p->scale, p->scale != 1.0 ? 1 : 0, stream) != hipSuccess)
+            return EFFT_ERR_HIP;
+        if (events && hipEventRecord(static_cast<hipEvent_t>(events[np]), stream) != hipSuccess)
+            return EFFT_ERR_HIP;
+        return EFFT_OK;
+    }
+    // C2R: pairing pass from in[0 .. N/2] into out[0 .. N/2), then the
+    // in-place backward N/2-point transform of out
+    if (events && hipEventRecord(static_cast<hipEvent_t>(events[0]), stream) != hipSuccess) return EFFT_ERR_HIP;
+    if (launch_c2r_pre(p->eb, in, out, h, p->tt_real, stream) != hipSuccess) return EFFT_ERR_HIP;
+    return run_c2c(p->inner, out, out, stream, events ? events + 1 : nullptr, events ? nevents - 1 : 0);
+}
+
+int run_c2c(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events,
+            int nevents)
 {
     if (events && nevents < int(p->passes.size()) + 1) return EFFT_ERR_ARG;
     for (size_t i = 0; i < p->passes.size(); ++i) {
@@ -335,6 +375,109 @@ const efft_plan_s *live(const efft_plan_t *plan)
     return plan->magic == PLAN_MAGIC ? plan : nullptr;
 }
 
+int validate_args(int q, int dtype, int dir, double scale)
+{
+    if (q < 0 || q > EFFT_MAX_LOG2N) return EFFT_ERR_SIZE;
+    if (!dtype_bytes(dtype)) return EFFT_ERR_DTYPE;
+    if (dir != EFFT_FORWARD && dir != EFFT_BACKWARD) return EFFT_ERR_DIR;
+    if (!(scale == scale) || scale == 0.0 || scale - scale != 0.0) return EFFT_ERR_ARG;  // NaN, 0, inf
+    return EFFT_OK;
+}
+
+// Two-level FP64 table of W_N^m for N = 2^q on the current device:
+// lo[2^h], hi[2^(q-h)], h = ceil(q/2).
+int make_tables(efft_plan_s *p, int q, TwTable *tt)
+{
+    const int h = (q + 1) / 2;
+    const int64_t n_lo = int64_t(1) << h, n_hi = int64_t(1) << (q - h);
+    p->table_bytes = (n_lo + n_hi) * int64_t(sizeof(double2));
+    if (hipMalloc(reinterpret_cast<void **>(&p->tables), size_t(p->table_bytes)) != hipSuccess) {
+        (void)hipGetLastError();
+        p->tables = nullptr;
+        return EFFT_ERR_ALLOC;
+    }
+    if (launch_twiddle_table(p->tables, n_lo, p->tables + n_lo, n_hi, h, q, nullptr) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(p->tables);
+        p->tables = nullptr;
+        return EFFT_ERR_HIP;
+    }
+    tt->lo = p->tables;
+    tt->hi = p->tables + n_lo;
+    tt->h = h;
+    tt->mask_n = (uint64_t(1) << q) - 1u;
+    tt->mask_lo = uint64_t(n_lo) - 1u;
+    return EFFT_OK;
+}
+
+efft_plan_s *create_c2c(int64_t n, int dtype, int dir, int inplace, double scale, int *status)
+{
+    efft_plan_s *p = new (std::nothrow) efft_plan_s();
+    if (!p) {
+        *status = EFFT_ERR_ALLOC;
+        return nullptr;
+    }
+    p->magic = PLAN_MAGIC;
+    p->n = n;
+    p->q = log2_exact(n);
+    p->dtype = dtype;
+    p->dir = dir;
+    p->inplace = inplace ? 1 : 0;
+    p->eb = dtype_bytes(dtype);
+    p->scale = scale;
+    p->kind = KIND_C2C;
+    p->inner = nullptr;
+    p->m = plan_digits(p->q, p->eb, p->inplace, p->digits);
+    if (p->m < 1) {
+        delete p;
+        *status = EFFT_ERR_SIZE;
+        return nullptr;
+    }
+    TwTable tt{};
+    *status = make_tables(p, p->q, &tt);
+    if (*status != EFFT_OK) {
+        delete p;
+        return nullptr;
+    }
+    build_passes(p, tt);
+    return p;
+}
+
+void free_plan(efft_plan_s *p)
+{
+    if (!p) return;
+    p->magic = 0;
+    if (p->tables) (void)hipFree(p->tables);
+    free_plan(p->inner);
+    delete p;
+}
+
+void register_plan(efft_plan_s *p)
+{
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_registry.insert(p);
+}
+
+// bytes of the input and output arrays of one execution
+int64_t in_bytes(const efft_plan_s *p)
+{
+    if (p->kind == KIND_R2C) return p->n * p->eb / 2;
+    if (p->kind == KIND_C2R) return (p->n / 2 + 1) * p->eb;
+    return p->n * p->eb;
+}
+int64_t out_bytes(const efft_plan_s *p)
+{
+    if (p->kind == KIND_R2C) return (p->n / 2 + 1) * p->eb;
+    if (p->kind == KIND_C2R) return p->n * p->eb / 2;
+    return p->n * p->eb;
+}
+
+bool overlaps(const efft_plan_s *p, const void *in, const void *out)
+{
+    const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+    return a < b + uintptr_t(out_bytes(p)) && b < a + uintptr_t(in_bytes(p));
+}
+
 }  // namespace
 
 extern "C" {
@@ -347,21 +490,28 @@ efft_plan_t *efft_plan(int64_t n, int dtype, int dir, int inplace)
 efft_plan_t *efft_plan_scaled(int64_t n, int dtype, int dir, int inplace, double scale)
 {
     const int q = log2_exact(n);
-    if (q < 0 || q > EFFT_MAX_LOG2N) {
-        g_last_error = EFFT_ERR_SIZE;
+    int status = validate_args(q, dtype, dir, scale);
+    if (status != EFFT_OK) {
+        g_last_error = status;
         return nullptr;
     }
-    const int eb = dtype_bytes(dtype);
-    if (!eb) {
-        g_last_error = EFFT_ERR_DTYPE;
+    efft_plan_s *p = create_c2c(n, dtype, dir, inplace, scale, &status);
+    if (!p) {
+        g_last_error = status;
         return nullptr;
     }
-    if (dir != EFFT_FORWARD && dir != EFFT_BACKWARD) {
-        g_last_error = EFFT_ERR_DIR;
-        return nullptr;
-    }
-    if (!(scale == scale) || scale == 0.0 || scale - scale != 0.0) {  // NaN, zero or infinite
-        g_last_error = EFFT_ERR_ARG;
+    register_plan(p);
+    g_last_error = EFFT_OK;
+    return p;
+}
+
+efft_plan_t *efft_plan_real(int64_t n, int dtype, int dir, double scale)
+{
+    const int q = log2_exact(n);
+    int status = validate_args(q, dtype, dir, scale);
+    if (status == EFFT_OK && q < 1) status = EFFT_ERR_SIZE;
+    if (status != EFFT_OK) {
+        g_last_error = status;
         return nullptr;
     }
     efft_plan_s *p = new (std::nothrow) efft_plan_s();
@@ -374,43 +524,28 @@ efft_plan_t *efft_plan_scaled(int64_t n, int dtype, int dir, int inplace, double
     p->q = q;
     p->dtype = dtype;
     p->dir = dir;
-    p->inplace = inplace ? 1 : 0;
-    p->eb = eb;
+    p->inplace = 0;
+    p->eb = dtype_bytes(dtype);
     p->scale = scale;
-    p->m = plan_digits(q, eb, p->inplace, p->digits);
-    if (p->m < 1) {
+    p->kind = dir == EFFT_FORWARD ? KIND_R2C : KIND_C2R;
+    status = make_tables(p, q, &p->tt_real);
+    if (status != EFFT_OK) {
         delete p;
-        g_last_error = EFFT_ERR_SIZE;
+        g_last_error = status;
         return nullptr;
     }
-    // two-level FP64 table: lo[2^h], hi[2^(q-h)], h = ceil(q/2)
-    const int h = (q + 1) / 2;
-    const int64_t n_lo = int64_t(1) << h, n_hi = int64_t(1) << (q - h);
-    p->table_bytes = (n_lo + n_hi) * int64_t(sizeof(double2));
-    if (hipMalloc(reinterpret_cast<void **>(&p->tables), size_t(p->table_bytes)) != hipSuccess) {
-        (void)hipGetLastError();
-        delete p;
-        g_last_error = EFFT_ERR_ALLOC;
-        return nullptr;
-    }
-    if (launch_twiddle_table(p->tables, n_lo, p->tables + n_lo, n_hi, h, q, nullptr) != hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess) {
+    // R2C: out-of-place forward N/2-point transform, scale applied by the
+    // pairing pass; C2R: in-place backward N/2-point transform on the output,
+    // scale applied by its last pass
+    p->inner = create_c2c(n / 2, dtype, dir, dir == EFFT_BACKWARD ? 1 : 0,
+                          dir == EFFT_BACKWARD ? scale : 1.0, &status);
+    if (!p->inner) {
         (void)hipFree(p->tables);
         delete p;
-        g_last_error = EFFT_ERR_HIP;
+        g_last_error = status;
         return nullptr;
     }
-    TwTable tt;
-    tt.lo = p->tables;
-    tt.hi = p->tables + n_lo;
-    tt.h = h;
-    tt.mask_n = uint64_t(n) - 1u;
-    tt.mask_lo = uint64_t(n_lo) - 1u;
-    build_passes(p, tt);
-    {
-        std::lock_guard<std::mutex> lk(g_reg_mu);
-        g_registry.insert(p);
-    }
+    register_plan(p);
     g_last_error = EFFT_OK;
     return p;
 }
@@ -433,9 +568,7 @@ int efft_exec_oop(const efft_plan_t *plan, const void *in, void *out, void *stre
     int v = validate_ptr(p, in);
     if (v == EFFT_OK) v = validate_ptr(p, out);
     if (v != EFFT_OK) return v;
-    const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
-    const uintptr_t bytes = uintptr_t(p->n) * uintptr_t(p->eb);
-    if (a < b + bytes && b < a + bytes) return EFFT_ERR_OVERLAP;
+    if (overlaps(p, in, out)) return EFFT_ERR_OVERLAP;
     return run(p, in, out, static_cast<hipStream_t>(stream), nullptr, 0);
 }
 
@@ -449,11 +582,7 @@ int efft_exec_events(const efft_plan_t *plan, const void *in, void *out, void *s
     if (v == EFFT_OK) v = validate_ptr(p, out);
     if (v != EFFT_OK) return v;
     if (p->inplace && in != out) return EFFT_ERR_PLAN_KIND;
-    if (!p->inplace) {
-        const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
-        const uintptr_t bytes = uintptr_t(p->n) * uintptr_t(p->eb);
-        if (a < b + bytes && b < a + bytes) return EFFT_ERR_OVERLAP;
-    }
+    if (!p->inplace && overlaps(p, in, out)) return EFFT_ERR_OVERLAP;
     return run(p, in, out, static_cast<hipStream_t>(stream), events, nevents);
 }
 
@@ -464,10 +593,8 @@ int efft_destroy(efft_plan_t *plan)
         std::lock_guard<std::mutex> lk(g_reg_mu);
         if (!g_registry.erase(plan)) return EFFT_ERR_BADPLAN;
     }
-    plan->magic = 0;
-    const hipError_t e = hipFree(plan->tables);
-    delete plan;
-    return e == hipSuccess ? EFFT_OK : EFFT_ERR_HIP;
+    free_plan(plan);
+    return EFFT_OK;
 }
 
 int efft_last_error(void) { return g_last_error; }
@@ -494,13 +621,14 @@ const char *efft_strerror(int status)
 int64_t efft_plan_bytes(const efft_plan_t *plan)
 {
     const efft_plan_s *p = live(plan);
-    return p ? p->table_bytes : -1;
+    if (!p) return -1;
+    return p->table_bytes + (p->inner ? p->inner->table_bytes : 0);
 }
 
 int efft_plan_passes(const efft_plan_t *plan)
 {
     const efft_plan_s *p = live(plan);
-    return p ? int(p->passes.size()) : -1;
+    return p ? total_passes(p) : -1;
 }
 
 int efft_schedule(int64_t n, int dtype, int inplace, int *log2_radix, int max_digits, int *passes)
@@ -521,6 +649,7 @@ int efft_schedule(int64_t n, int dtype, int inplace, int *log2_radix, int max_di
     probe.inplace = inplace ? 1 : 0;
     probe.eb = eb;
     probe.scale = 1.0;
+    probe.kind = KIND_C2C;
     probe.m = plan_digits(q, eb, probe.inplace, probe.digits);
     if (probe.m < 1) return EFFT_ERR_SIZE;
     if (probe.m > max_digits) return EFFT_ERR_ARG;

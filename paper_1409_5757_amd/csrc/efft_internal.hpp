@@ -95,6 +95,10 @@ hipError_t launch_stage(int dtype_bytes, int layout, int logl, int lines, int se
 hipError_t launch_swap(int dtype_bytes, const SwapParams &p, hipStream_t stream);
 hipError_t launch_twiddle_table(double2 *lo, int64_t n_lo, double2 *hi, int64_t n_hi, int h,
                                 int q, hipStream_t stream);
+hipError_t launch_r2c_post(int dtype_bytes, void *z, int64_t h, const TwTable &tt, double scale,
+                           int apply_scale, hipStream_t stream);
+hipError_t launch_c2r_pre(int dtype_bytes, const void *f, void *z, int64_t h, const TwTable &tt,
+                          hipStream_t stream);
 // while on (per host thread), launch_stage / launch_swap only check that a
 // kernel exists for the arguments and launch nothing
 void set_dry_run(bool on);
