@@ -53,23 +53,24 @@ def traffic_record(workload_key: str, pass_index: int):
     return None if p is None else p.get("hbm_bytes")
 
 
-def time_transform(plan, x, steps: int, warmup: int):
+def time_transform(plan, x, steps: int, warmup: int, scratch=None):
     """Warm up, then time exactly `steps` transforms; per-pass event times."""
     import torch
     for _ in range(warmup):
-        plan.execute(x)
+        plan.execute(x, scratch=scratch)
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(plan.passes + 1)] for _ in range(steps)]
+    npass = plan.passes if scratch is None else plan.scratch_passes
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(npass + 1)] for _ in range(steps)]
     for row in evs:  # materialise every hipEvent before the timed region
         for e in row:
             e.record()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for row in evs:
-        plan.execute_events(x, x, [e.cuda_event for e in row])
+        plan.execute_events(x, x, [e.cuda_event for e in row], scratch=scratch)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per_pass = [sum(row[i].elapsed_time(row[i + 1]) for row in evs) / steps for i in range(plan.passes)]
+    per_pass = [sum(row[i].elapsed_time(row[i + 1]) for row in evs) / steps for i in range(npass)]
     event_step = sum(row[0].elapsed_time(row[-1]) for row in evs) / steps
     return wall / steps * 1e3, event_step, per_pass
 
@@ -177,7 +178,17 @@ def main() -> int:
         "hbm_GBps_whole_transform": round(passes * bytes_pass / (ms_events * 1e-3) / 1e9, 1),
         "passes_detail": passes_out,
     }
-    del x
+    # the same plan with a scratch array of N elements (one pass fewer, 2x memory)
+    scratch = plan.make_scratch()
+    ms_s, ev_s, pp_s = time_transform(plan, x, args.steps, args.warmup, scratch=scratch)
+    result["with_scratch"] = {
+        "workload": f"same transform, in place with a caller-provided scratch array of N elements "
+                    f"({n * 16 / 2**30:.0f} GiB)",
+        "value": round(5 * n * q / (ms_s * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "ms_per_step": round(ms_s, 4),
+        "passes": plan.scratch_passes,
+        "passes_detail": [{"pass": i, "ms": round(t, 4), "GBps": round(bytes_pass / (t * 1e-3) / 1e9, 1)}
+                          for i, t in enumerate(pp_s)]}
+    del x, scratch
     torch.cuda.empty_cache()
 
     if not args.no_fp32:

@@ -136,13 +136,33 @@ int efft_exec(const efft_plan_t *plan, void *data, void *stream);
 int efft_exec_oop(const efft_plan_t *plan, const void *in, void *out, void *stream);
 
 /*
- * Same work as efft_exec (in == out, in-place plan) or efft_exec_oop (other
- * plans), additionally recording events[i] (hipEvent_t, created by the
- * caller) on stream just before kernel pass i and events[npass] after the
- * last one, so that per-pass durations can be read with
- * hipEventElapsedTime.  nevents must be at least efft_plan_passes(plan) + 1.
+ * In-place transform like efft_exec, using a caller-owned device scratch
+ * array of efft_scratch_bytes(plan) bytes (N elements; it must not overlap
+ * data).  With scratch the digit-reversal pass disappears: the last sub-FFT
+ * pass reads rows of the scratch array and writes its results straight to
+ * their natural positions in data, so the transform makes one pass fewer over
+ * memory.  This trades the extra array for speed, as the paper's EFFT does
+ * with its scratch array (Section 3.1).  The scratch contents are undefined
+ * afterwards.  For plans that gain nothing from scratch (N <= 2^12),
+ * efft_scratch_bytes returns 0 and this call is efft_exec (scratch may be NULL).
  */
-int efft_exec_events(const efft_plan_t *plan, const void *in, void *out, void *stream,
+int efft_exec_scratch(const efft_plan_t *plan, void *data, void *scratch, void *stream);
+
+/* Scratch bytes efft_exec_scratch uses (0 if none helps); -1 for a bad handle. */
+int64_t efft_scratch_bytes(const efft_plan_t *plan);
+
+/* Kernel launches of one efft_exec_scratch call; -1 for a bad handle. */
+int efft_plan_passes_scratch(const efft_plan_t *plan);
+
+/*
+ * Same work as efft_exec (in == out, in-place plan; with scratch != NULL as
+ * efft_exec_scratch) or efft_exec_oop (other plans), additionally recording
+ * events[i] (hipEvent_t, created by the caller) on stream just before kernel
+ * pass i and events[npass] after the last one, so that per-pass durations can
+ * be read with hipEventElapsedTime.  nevents must be at least the number of
+ * passes + 1 (efft_plan_passes, or efft_plan_passes_scratch with scratch).
+ */
+int efft_exec_events(const efft_plan_t *plan, const void *in, void *out, void *scratch, void *stream,
                      void **events, int nevents);
 
 /* Free the plan's device tables; NULL is a no-op returning EFFT_OK; a handle

@@ -45,8 +45,14 @@ def _bind(lib):
     lib.efft_exec.restype = ci
     lib.efft_exec_oop.argtypes = [vp, vp, vp, vp]
     lib.efft_exec_oop.restype = ci
-    lib.efft_exec_events.argtypes = [vp, vp, vp, vp, ctypes.POINTER(vp), ci]
+    lib.efft_exec_events.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(vp), ci]
     lib.efft_exec_events.restype = ci
+    lib.efft_exec_scratch.argtypes = [vp, vp, vp, vp]
+    lib.efft_exec_scratch.restype = ci
+    lib.efft_scratch_bytes.argtypes = [vp]
+    lib.efft_scratch_bytes.restype = i64
+    lib.efft_plan_passes_scratch.argtypes = [vp]
+    lib.efft_plan_passes_scratch.restype = ci
     lib.efft_destroy.argtypes = [vp]
     lib.efft_destroy.restype = ci
     lib.efft_last_error.argtypes = []

@@ -53,6 +53,14 @@ class Plan:
             raise EfftError(self.lib.efft_last_error(), "efft_plan")
         self.handle = ctypes.c_void_p(h)
         self.passes = self.lib.efft_plan_passes(self.handle)
+        self.scratch_passes = self.lib.efft_plan_passes_scratch(self.handle)
+        self.scratch_bytes = int(self.lib.efft_scratch_bytes(self.handle))
+
+    def make_scratch(self) -> torch.Tensor | None:
+        """A scratch tensor for ``execute(..., scratch=...)`` (None if unused)."""
+        if self.scratch_bytes <= 0:
+            return None
+        return torch.empty(self.n, dtype=self.dtype, device=self.device)
 
     def _check(self, t: torch.Tensor, name: str):
         if t.dtype != self.dtype:
@@ -64,14 +72,24 @@ class Plan:
         if not t.is_contiguous():
             raise ValueError(f"{name}: tensor must be contiguous")
 
-    def execute(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """Transform every length-N row of x; in place for in-place plans."""
+    def execute(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None,
+                scratch: torch.Tensor | None = None) -> torch.Tensor:
+        """Transform every length-N row of x; in place for in-place plans
+        (with ``scratch``, an N-element tensor of the plan's dtype, one pass
+        fewer)."""
         self._check(x, "input")
         s = ctypes.c_void_p((stream or torch.cuda.current_stream(self.device)).cuda_stream)
         rows = x.numel() // self.n if self.n else 0
         xp = x.data_ptr()
         step = self.n * x.element_size()
         if self.inplace:
+            if scratch is not None:
+                self._check(scratch, "scratch")
+                sp = ctypes.c_void_p(scratch.data_ptr())
+                for r in range(rows):
+                    _lib.check(self.lib.efft_exec_scratch(self.handle, ctypes.c_void_p(xp + r * step), sp, s),
+                               "efft_exec_scratch")
+                return x
             for r in range(rows):
                 _lib.check(self.lib.efft_exec(self.handle, ctypes.c_void_p(xp + r * step), s), "efft_exec")
             return x
@@ -84,13 +102,15 @@ class Plan:
                                               ctypes.c_void_p(op + r * step), s), "efft_exec_oop")
         return out
 
-    def execute_events(self, x: torch.Tensor, out: torch.Tensor, events, stream=None) -> None:
+    def execute_events(self, x: torch.Tensor, out: torch.Tensor, events, stream=None,
+                       scratch: torch.Tensor | None = None) -> None:
         """One transform of a single signal, recording caller-created hipEvents
         before each pass and after the last (``len(events) == passes + 1``)."""
         s = ctypes.c_void_p((stream or torch.cuda.current_stream(self.device)).cuda_stream)
         arr = (ctypes.c_void_p * len(events))(*events)
+        sc = ctypes.c_void_p(scratch.data_ptr()) if scratch is not None else None
         _lib.check(self.lib.efft_exec_events(self.handle, ctypes.c_void_p(x.data_ptr()),
-                                             ctypes.c_void_p(out.data_ptr()), s, arr, len(events)),
+                                             ctypes.c_void_p(out.data_ptr()), sc, s, arr, len(events)),
                    "efft_exec_events")
 
     def device_bytes(self) -> int:
@@ -160,7 +180,7 @@ class RealPlan:
         s = ctypes.c_void_p((stream or torch.cuda.current_stream(self.device)).cuda_stream)
         arr = (ctypes.c_void_p * len(events))(*events)
         _lib.check(self.lib.efft_exec_events(self.handle, ctypes.c_void_p(x.data_ptr()),
-                                             ctypes.c_void_p(out.data_ptr()), s, arr, len(events)),
+                                             ctypes.c_void_p(out.data_ptr()), None, s, arr, len(events)),
                    "efft_exec_events")
 
     def close(self) -> None:

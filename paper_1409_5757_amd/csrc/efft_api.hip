@@ -35,8 +35,12 @@ namespace {
 constexpr uint64_t PLAN_MAGIC = 0x45464654504c414eULL;  // "EFFTPLAN"
 constexpr int MAX_DIGITS = 6;
 
+// which array a pass reads or writes
+enum Buf { BUF_IN = 0, BUF_OUT = 1, BUF_SCRATCH = 2 };
+
 struct Pass {
     bool swap;
+    int src, dst;  // Buf
     int layout, logl, lines, sets;
     StageParams sp;  // src/dst filled at exec time
     SwapParams wp;   // data filled at exec time
@@ -149,6 +153,9 @@ struct efft_plan_s {
     int m;
     int digits[MAX_DIGITS];
     std::vector<Pass> passes;
+    // in-place plans: the same transform with a caller-provided scratch array
+    // of N elements, one pass shorter (empty when that gains nothing)
+    std::vector<Pass> scratch_passes;
     double scale;
     double2 *tables;
     int64_t table_bytes;
@@ -178,18 +185,72 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt);
 
 // The output scale is applied by the last sub-FFT pass (a trailing
 // digit-reversal pass only permutes).
+void build_scratch_passes(efft_plan_s *p, const TwTable &tt);
+
+void apply_scale_to_last(std::vector<Pass> &v, double scale)
+{
+    if (scale == 1.0) return;
+    for (size_t i = v.size(); i-- > 0;) {
+        if (!v[i].swap) {
+            v[i].sp.apply_scale = 1;
+            v[i].sp.scale = scale;
+            return;
+        }
+    }
+}
+
 void build_passes(efft_plan_s *p, const TwTable &tt)
 {
     build_passes_unscaled(p, tt);
-    if (p->scale != 1.0) {
-        for (size_t i = p->passes.size(); i-- > 0;) {
-            if (!p->passes[i].swap) {
-                p->passes[i].sp.apply_scale = 1;
-                p->passes[i].sp.scale = p->scale;
-                break;
-            }
-        }
+    // the first pass reads the input; every later pass works in place on out
+    for (size_t i = 0; i < p->passes.size(); ++i) {
+        p->passes[i].src = i == 0 ? BUF_IN : BUF_OUT;
+        p->passes[i].dst = BUF_OUT;
     }
+    apply_scale_to_last(p->passes, p->scale);
+    p->scratch_passes.clear();
+    if (p->inplace && p->m >= 2) {
+        build_scratch_passes(p, tt);
+        apply_scale_to_last(p->scratch_passes, p->scale);
+    }
+}
+
+// Scratch schedule of an in-place plan: the sub-FFT passes of digits
+// 1 .. m-1 run as in the in-place schedule, the first from the data into the
+// scratch array and the others in place on it; the last digit's pass reads
+// contiguous rows of the scratch array and writes each transformed row as a
+// column of the data array at its natural position, so no digit-reversal
+// pass is needed.
+void build_scratch_passes(efft_plan_s *p, const TwTable &tt)
+{
+    const int m = p->m;
+    for (int j = 0; j + 1 < m; ++j) {
+        Pass ps = p->passes[size_t(j)];
+        ps.src = j == 0 ? BUF_IN : BUF_SCRATCH;
+        ps.dst = BUF_SCRATCH;
+        p->scratch_passes.push_back(ps);
+    }
+    const int64_t n = p->n;
+    const int dl = p->digits[m - 1];
+    const int64_t L = int64_t(1) << dl;
+    Pass ps{};
+    ps.swap = false;
+    ps.src = BUF_SCRATCH;
+    ps.dst = BUF_OUT;
+    ps.logl = dl;
+    ps.layout = LAYOUT_ROW2COL;
+    ps.lines = col_lines(p->eb, dl, n / L, true);
+    ps.sets = 1;
+    ps.sp = base_params(p, tt);
+    ps.sp.s = 1;
+    ps.sp.B = L;
+    ps.sp.n_over_l = uint64_t(n / L);
+    ps.sp.row_mul = n / L;
+    ps.sp.rev.nd = 0;
+    for (int i = 0; i + 1 < m; ++i) ps.sp.rev.bits[ps.sp.rev.nd++] = p->digits[i];  // k_1 lowest
+    ps.sp.order = col_order(n / L);
+    ps.sp.ntiles = (n / L) / ps.lines;
+    p->scratch_passes.push_back(ps);
 }
 
 void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
@@ -344,29 +405,35 @@ int run(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, voi
     return run_c2c(p->inner, out, out, stream, events ? events + 1 : nullptr, events ? nevents - 1 : 0);
 }
 
-int run_c2c(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events,
-            int nevents)
+int run_passes(const std::vector<Pass> &passes, int eb, const void *in, void *out, void *scratch,
+               hipStream_t stream, void **events, int nevents)
 {
-    if (events && nevents < int(p->passes.size()) + 1) return EFFT_ERR_ARG;
-    for (size_t i = 0; i < p->passes.size(); ++i) {
-        Pass ps = p->passes[i];
+    if (events && nevents < int(passes.size()) + 1) return EFFT_ERR_ARG;
+    for (size_t i = 0; i < passes.size(); ++i) {
+        Pass ps = passes[i];
         if (events && hipEventRecord(static_cast<hipEvent_t>(events[i]), stream) != hipSuccess)
             return EFFT_ERR_HIP;
+        void *bufs[3] = {const_cast<void *>(in), out, scratch};
         hipError_t e;
         if (ps.swap) {
-            ps.wp.data = out;
-            e = launch_swap(p->eb, ps.wp, stream);
+            ps.wp.data = bufs[ps.dst];
+            e = launch_swap(eb, ps.wp, stream);
         } else {
-            // the first pass reads the input; every later pass works in place on out
-            ps.sp.src = (i == 0) ? in : out;
-            ps.sp.dst = out;
-            e = launch_stage(p->eb, ps.layout, ps.logl, ps.lines, ps.sets, ps.sp, stream);
+            ps.sp.src = bufs[ps.src];
+            ps.sp.dst = bufs[ps.dst];
+            e = launch_stage(eb, ps.layout, ps.logl, ps.lines, ps.sets, ps.sp, stream);
         }
         if (e != hipSuccess) return EFFT_ERR_HIP;
     }
-    if (events && hipEventRecord(static_cast<hipEvent_t>(events[p->passes.size()]), stream) != hipSuccess)
+    if (events && hipEventRecord(static_cast<hipEvent_t>(events[passes.size()]), stream) != hipSuccess)
         return EFFT_ERR_HIP;
     return EFFT_OK;
+}
+
+int run_c2c(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events,
+            int nevents)
+{
+    return run_passes(p->passes, p->eb, in, out, nullptr, stream, events, nevents);
 }
 
 const efft_plan_s *live(const efft_plan_t *plan)
@@ -472,6 +539,15 @@ int64_t out_bytes(const efft_plan_s *p)
     return p->n * p->eb;
 }
 
+int validate_scratch(const efft_plan_s *p, const void *data, const void *scratch)
+{
+    int v = validate_ptr(p, scratch);
+    if (v != EFFT_OK) return v;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(data), b = reinterpret_cast<uintptr_t>(scratch);
+    const uintptr_t bytes = uintptr_t(p->n) * uintptr_t(p->eb);
+    return (a < b + bytes && b < a + bytes) ? EFFT_ERR_OVERLAP : EFFT_OK;
+}
+
 bool overlaps(const efft_plan_s *p, const void *in, const void *out)
 {
     const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
@@ -572,8 +648,8 @@ int efft_exec_oop(const efft_plan_t *plan, const void *in, void *out, void *stre
     return run(p, in, out, static_cast<hipStream_t>(stream), nullptr, 0);
 }
 
-int efft_exec_events(const efft_plan_t *plan, const void *in, void *out, void *stream, void **events,
-                     int nevents)
+int efft_exec_events(const efft_plan_t *plan, const void *in, void *out, void *scratch, void *stream,
+                     void **events, int nevents)
 {
     const efft_plan_s *p = live(plan);
     if (!p) return plan ? EFFT_ERR_BADPLAN : EFFT_ERR_NULLPTR;
@@ -583,7 +659,41 @@ int efft_exec_events(const efft_plan_t *plan, const void *in, void *out, void *s
     if (v != EFFT_OK) return v;
     if (p->inplace && in != out) return EFFT_ERR_PLAN_KIND;
     if (!p->inplace && overlaps(p, in, out)) return EFFT_ERR_OVERLAP;
+    if (scratch && !p->scratch_passes.empty()) {
+        v = validate_scratch(p, out, scratch);
+        if (v != EFFT_OK) return v;
+        return run_passes(p->scratch_passes, p->eb, in, out, scratch, static_cast<hipStream_t>(stream),
+                          events, nevents);
+    }
     return run(p, in, out, static_cast<hipStream_t>(stream), events, nevents);
+}
+
+int efft_exec_scratch(const efft_plan_t *plan, void *data, void *scratch, void *stream)
+{
+    const efft_plan_s *p = live(plan);
+    if (!p) return plan ? EFFT_ERR_BADPLAN : EFFT_ERR_NULLPTR;
+    if (!p->inplace) return EFFT_ERR_PLAN_KIND;
+    int v = validate_ptr(p, data);
+    if (v != EFFT_OK) return v;
+    if (p->scratch_passes.empty()) return run(p, data, data, static_cast<hipStream_t>(stream), nullptr, 0);
+    v = validate_scratch(p, data, scratch);
+    if (v != EFFT_OK) return v;
+    return run_passes(p->scratch_passes, p->eb, data, data, scratch, static_cast<hipStream_t>(stream),
+                      nullptr, 0);
+}
+
+int64_t efft_scratch_bytes(const efft_plan_t *plan)
+{
+    const efft_plan_s *p = live(plan);
+    if (!p) return -1;
+    return p->scratch_passes.empty() ? 0 : p->n * p->eb;
+}
+
+int efft_plan_passes_scratch(const efft_plan_t *plan)
+{
+    const efft_plan_s *p = live(plan);
+    if (!p) return -1;
+    return p->scratch_passes.empty() ? total_passes(p) : int(p->scratch_passes.size());
 }
 
 int efft_destroy(efft_plan_t *plan)
@@ -657,7 +767,9 @@ int efft_schedule(int64_t n, int dtype, int inplace, int *log2_radix, int max_di
     build_passes(&probe, tt);
     set_dry_run(true);
     int status = EFFT_OK;
-    for (const Pass &ps : probe.passes) {
+    std::vector<Pass> all = probe.passes;
+    all.insert(all.end(), probe.scratch_passes.begin(), probe.scratch_passes.end());
+    for (const Pass &ps : all) {
         const hipError_t e = ps.swap ? launch_swap(eb, ps.wp, nullptr)
                                      : launch_stage(eb, ps.layout, ps.logl, ps.lines, ps.sets, ps.sp, nullptr);
         if (e != hipSuccess) status = EFFT_ERR_SIZE;

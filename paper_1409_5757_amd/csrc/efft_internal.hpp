@@ -12,8 +12,11 @@ enum Layout : int {
     LAYOUT_ROW = 0,     // contiguous lines (stride 1), one or more per workgroup
     LAYOUT_COL = 1,     // strided lines; a workgroup takes W adjacent lines, so
                         // every row of its tile is one contiguous W-element run
-    LAYOUT_COL2ROW = 2  // strided lines read as LAYOUT_COL, each written back
+    LAYOUT_COL2ROW = 2, // strided lines read as LAYOUT_COL, each written back
                         // as a contiguous row at a digit-reversed row index
+    LAYOUT_ROW2COL = 3  // contiguous rows read from a scratch array, each
+                        // written as a strided column of the output, in
+                        // natural order (the last pass of a scratch plan)
 };
 
 // Twiddle applied to output k of line (block b, offset o) of a pass.
@@ -54,8 +57,10 @@ struct StageParams {
     int64_t ntiles;      // workgroups in the grid
     uint64_t n_over_l;   // N / L, scales the in-line Stockham twiddles
     uint64_t tw_scale;   // see TwMode
-    int64_t row_mul;     // LAYOUT_COL2ROW: line o's row starts at row_mul * rev(o)
-    Digits rev;          // digits of o (COL2ROW) or of blk (TW_REVBLOCK)
+    int64_t row_mul;     // LAYOUT_COL2ROW: line o's row starts at row_mul * rev(o);
+                         // LAYOUT_ROW2COL: column stride of the output
+    Digits rev;          // digits of o (COL2ROW), of blk (TW_REVBLOCK) or of the
+                         // output column index (ROW2COL, whose source row is its reversal)
     TwTable tt;
     double scale;        // multiplies every output when apply_scale is set
     int twmode;

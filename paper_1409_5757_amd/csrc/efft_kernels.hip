@@ -240,13 +240,15 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
     constexpr int E = LineGeom<L>::E;
     constexpr int P = LineGeom<L>::P;
     constexpr int PADDED = LineGeom<L>::PADDED;
-    constexpr bool NEED_LDS = (Radices<LOGL>::NSTEPS > 1) || (LAYOUT == LAYOUT_COL2ROW);
+    constexpr bool NEED_LDS =
+        (Radices<LOGL>::NSTEPS > 1) || (LAYOUT == LAYOUT_COL2ROW) || (LAYOUT == LAYOUT_ROW2COL);
     static_assert(LAYOUT != LAYOUT_COL2ROW || SETS == 1, "one line set for row writes");
     __shared__ V lds[NEED_LDS ? LINES * PADDED : 1];
 
+    static_assert(LAYOUT != LAYOUT_ROW2COL || SETS == 1, "one line set for column writes");
     const int tid = threadIdx.x;
     int c, t;
-    if constexpr (LAYOUT == LAYOUT_ROW) {
+    if constexpr (LAYOUT == LAYOUT_ROW || LAYOUT == LAYOUT_ROW2COL) {
         t = tid % P;
         c = tid / P;
     } else {
@@ -262,9 +264,17 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
 #pragma unroll
     for (int st = 0; st < SETS; ++st) {
         const int64_t line = tile * (LINES * SETS) + st * LINES + c;
-        blkv[st] = line / sp.s;
-        off[st] = line - blkv[st] * sp.s;
-        base[st] = blkv[st] * sp.B + off[st];
+        if constexpr (LAYOUT == LAYOUT_ROW2COL) {
+            // the tile's lines are LINES consecutive output columns; the source
+            // row of output column `line` is its digit reversal
+            blkv[st] = int64_t(digit_reverse(uint64_t(line), sp.rev));
+            off[st] = 0;
+            base[st] = blkv[st] * L;
+        } else {
+            blkv[st] = line / sp.s;
+            off[st] = line - blkv[st] * sp.s;
+            base[st] = blkv[st] * sp.B + off[st];
+        }
     }
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -280,7 +290,23 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
     }
 
     V *lds_line = lds + (NEED_LDS ? c * PADDED : 0);
-    if constexpr (LAYOUT != LAYOUT_COL2ROW) {
+    if constexpr (LAYOUT == LAYOUT_ROW2COL) {
+        // outputs land in LDS in natural order; re-read them across the tile's
+        // lines (lane = line) and write output k of column `line` at
+        // line + row_mul * k, so each store covers LINES consecutive elements
+        line_fft<V, LOGL, true>(v[0], lds_line, t, sp.tt, sp.n_over_l);
+        __syncthreads();
+        const int c2 = tid % LINES;
+        const int t2 = tid / LINES;
+        const int64_t col = tile * LINES + c2;
+        const V *col_lds = lds + c2 * PADDED;
+        V w[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) w[i] = col_lds[lds_pad(t2 + P * i)];
+        finish_outputs<V, E>(w, sp);
+#pragma unroll
+        for (int i = 0; i < E; ++i) dst[col + sp.row_mul * int64_t(t2 + P * i)] = w[i];
+    } else if constexpr (LAYOUT != LAYOUT_COL2ROW) {
 #pragma unroll
         for (int st = 0; st < SETS; ++st) {
             if (st > 0) __syncthreads();  // the previous set has finished with LDS
@@ -437,6 +463,12 @@ static hipError_t dispatch_logl(int layout, int lines, int sets, const StagePara
             if (lines == WMAX) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL2ROW>(p, stream);
             if constexpr (WMIN != WMAX) {
                 if (lines == WMIN) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL2ROW>(p, stream);
+            }
+        }
+        if (layout == LAYOUT_ROW2COL && sets == 1) {
+            if (lines == WMAX) return launch_one<T, LOGL, WMAX, 1, LAYOUT_ROW2COL>(p, stream);
+            if constexpr (WMIN != WMAX) {
+                if (lines == WMIN) return launch_one<T, LOGL, WMIN, 1, LAYOUT_ROW2COL>(p, stream);
             }
         }
     }

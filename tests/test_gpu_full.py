@@ -88,6 +88,24 @@ def test_c2_2p30_complex128_in_place_sampled_and_round_trip():
     assert rt < 1e-14
 
 
+def test_c2_2p30_complex128_scratch_schedule_bitwise():
+    """The scratch schedule of the benchmark plan gives the same bits as the
+    scratch-free schedule, whose parity the previous test establishes."""
+    n = 1 << 30
+    torch.cuda.empty_cache()
+    a = torch.empty(n, dtype=torch.complex128, device=DEV)
+    inputs.fill_uniform_torch(a, seed=0)
+    b = a.clone()
+    plan = api.get_plan(n, torch.complex128, -1, True, 1.0, DEV)
+    plan.execute(a)
+    scratch = plan.make_scratch()
+    plan.execute(b, scratch=scratch)
+    torch.cuda.synchronize()
+    assert plan.scratch_passes == 3 and plan.passes == 4
+    same = all(torch.equal(a[i:i + (1 << 26)], b[i:i + (1 << 26)]) for i in range(0, n, 1 << 26))
+    assert same
+
+
 def test_c2_2p30_complex128_tones_full_spectrum():
     """The 8-tone variant: exact peaks N e^{i phi} and zero elsewhere, checked
     on all 2^30 bins on the device."""

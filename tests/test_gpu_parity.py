@@ -167,3 +167,44 @@ def test_plan_events_cover_every_pass():
     times = [evs[i].elapsed_time(evs[i + 1]) for i in range(p.passes)]
     assert all(t > 0 for t in times)
     assert rel_l2(x.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_scratch_schedule_matches_in_place_bitwise(dtype):
+    """With a scratch array the in-place plan drops its digit-reversal pass; the
+    sub-FFT arithmetic is the same, so the result must be bit-identical to the
+    scratch-free schedule (and both match the oracle)."""
+    for q in (1, 12, 13, 14, 15, 17, 20, 22, 24):
+        n = 1 << q
+        for direction in (-1, 1):
+            xh = host_input("uniform", 500 + q, n, dtype)
+            plan = api.get_plan(n, dtype, direction, True, 1.0, torch.device("cuda", 0))
+            a = torch.from_numpy(xh).cuda()
+            b = a.clone()
+            plan.execute(a)
+            scratch = plan.make_scratch()
+            if q >= 13:
+                assert scratch is not None and plan.scratch_passes == plan.passes - 1
+            plan.execute(b, scratch=scratch)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b), (q, direction)
+            err = rel_l2(b.cpu().numpy(), oracle.fft(xh, direction))
+            assert err <= TOL[dtype], (q, err)
+
+
+def test_scratch_error_paths():
+    lib = _lib.load()
+    dev = torch.device("cuda", 0)
+    n = 1 << 14
+    ip = api.Plan(n, torch.complex128, -1, True, device=dev)
+    oop = api.Plan(n, torch.complex128, -1, False, device=dev)
+    assert ip.scratch_bytes == n * 16 and oop.scratch_bytes == 0
+    buf = torch.zeros(3 * n, dtype=torch.complex128, device=dev)
+    base = buf.data_ptr()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    data, scr = ctypes.c_void_p(base), ctypes.c_void_p(base + n * 16)
+    assert lib.efft_exec_scratch(oop.handle, data, scr, s) == -6                        # wrong kind
+    assert lib.efft_exec_scratch(ip.handle, data, ctypes.c_void_p(base + 8 * n), s) == -7  # overlap
+    assert lib.efft_exec_scratch(ip.handle, data, ctypes.c_void_p(base + n * 16 + 8), s) == -5  # align
+    assert lib.efft_exec_scratch(ip.handle, data, None, s) == -4
+    torch.cuda.synchronize()
