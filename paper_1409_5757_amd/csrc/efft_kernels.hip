@@ -227,60 +227,55 @@ __device__ __forceinline__ int64_t order_tiles(int64_t bid, int64_t ntiles, int 
     return bid;
 }
 
-// One pass: each workgroup transforms LINES * SETS lines.  Thread (c, t)
-// owns points t + P*i of lines c + LINES*set (set < SETS): the SETS line sets
-// are loaded together, so a strided tile row is one LINES*SETS-element run,
-// and then transformed one set at a time through the same LDS buffer.
-template <typename T, int LOGL, int LINES, int SETS, int LAYOUT>
-__global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
-    stage_kernel(StageParams sp)
+// Addresses of one tile's lines for the thread's line c (one per set).
+template <int SETS> struct TileLines {
+    int64_t tile;
+    int64_t base[SETS], off[SETS], blk[SETS];
+};
+
+template <int L, int LINES, int SETS, int LAYOUT>
+__device__ __forceinline__ TileLines<SETS> tile_lines(int64_t tile, int c, const StageParams &sp)
 {
-    using V = typename vec2<T>::type;
-    constexpr int L = 1 << LOGL;
-    constexpr int E = LineGeom<L>::E;
-    constexpr int P = LineGeom<L>::P;
-    constexpr int PADDED = LineGeom<L>::PADDED;
-    constexpr bool NEED_LDS =
-        (Radices<LOGL>::NSTEPS > 1) || (LAYOUT == LAYOUT_COL2ROW) || (LAYOUT == LAYOUT_ROW2COL);
-    static_assert(LAYOUT != LAYOUT_COL2ROW || SETS == 1, "one line set for row writes");
-    __shared__ V lds[NEED_LDS ? LINES * PADDED : 1];
-
-    static_assert(LAYOUT != LAYOUT_ROW2COL || SETS == 1, "one line set for column writes");
-    const int tid = threadIdx.x;
-    int c, t;
-    if constexpr (LAYOUT == LAYOUT_ROW || LAYOUT == LAYOUT_ROW2COL) {
-        t = tid % P;
-        c = tid / P;
-    } else {
-        c = tid % LINES;
-        t = tid / LINES;
-    }
-    const int64_t tile = order_tiles(blockIdx.x, sp.ntiles, sp.order);
-    const V *src = static_cast<const V *>(sp.src);
-    V *dst = static_cast<V *>(sp.dst);
-
-    int64_t base[SETS], off[SETS], blkv[SETS];
-    V v[SETS][E];
+    TileLines<SETS> a;
+    a.tile = tile;
 #pragma unroll
     for (int st = 0; st < SETS; ++st) {
         const int64_t line = tile * (LINES * SETS) + st * LINES + c;
         if constexpr (LAYOUT == LAYOUT_ROW2COL) {
             // the tile's lines are LINES consecutive output columns; the source
             // row of output column `line` is its digit reversal
-            blkv[st] = int64_t(digit_reverse(uint64_t(line), sp.rev));
-            off[st] = 0;
-            base[st] = blkv[st] * L;
+            a.blk[st] = int64_t(digit_reverse(uint64_t(line), sp.rev));
+            a.off[st] = 0;
+            a.base[st] = a.blk[st] * L;
         } else {
-            blkv[st] = line / sp.s;
-            off[st] = line - blkv[st] * sp.s;
-            base[st] = blkv[st] * sp.B + off[st];
+            a.blk[st] = line / sp.s;
+            a.off[st] = line - a.blk[st] * sp.s;
+            a.base[st] = a.blk[st] * sp.B + a.off[st];
         }
     }
+    return a;
+}
+
+template <typename V, int E, int P, int SETS>
+__device__ __forceinline__ void load_tile(V (&v)[SETS][E], const TileLines<SETS> &a, const V *src, int t,
+                                          int64_t s)
+{
 #pragma unroll
     for (int i = 0; i < E; ++i) {
 #pragma unroll
-        for (int st = 0; st < SETS; ++st) v[st][i] = src[base[st] + sp.s * int64_t(t + P * i)];
+        for (int st = 0; st < SETS; ++st) v[st][i] = src[a.base[st] + s * int64_t(t + P * i)];
     }
+}
+
+// Transform the loaded tile and store it (the layout decides where).
+template <typename V, int LOGL, int LINES, int SETS, int LAYOUT>
+__device__ __forceinline__ void process_tile(V (&v)[SETS][LineGeom<(1 << LOGL)>::E], const TileLines<SETS> &a,
+                                             V *lds, V *dst, int c, int t, int tid, const StageParams &sp)
+{
+    constexpr int L = 1 << LOGL;
+    constexpr int E = LineGeom<L>::E;
+    constexpr int P = LineGeom<L>::P;
+    constexpr int PADDED = LineGeom<L>::PADDED;
     if (sp.conj) {
 #pragma unroll
         for (int st = 0; st < SETS; ++st) {
@@ -288,8 +283,7 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
             for (int i = 0; i < E; ++i) v[st][i].y = -v[st][i].y;
         }
     }
-
-    V *lds_line = lds + (NEED_LDS ? c * PADDED : 0);
+    V *lds_line = lds + c * PADDED;
     if constexpr (LAYOUT == LAYOUT_ROW2COL) {
         // outputs land in LDS in natural order; re-read them across the tile's
         // lines (lane = line) and write output k of column `line` at
@@ -298,7 +292,7 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
         __syncthreads();
         const int c2 = tid % LINES;
         const int t2 = tid / LINES;
-        const int64_t col = tile * LINES + c2;
+        const int64_t col = a.tile * LINES + c2;
         const V *col_lds = lds + c2 * PADDED;
         V w[E];
 #pragma unroll
@@ -312,13 +306,13 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
             if (st > 0) __syncthreads();  // the previous set has finished with LDS
             line_fft<V, LOGL, false>(v[st], lds_line, t, sp.tt, sp.n_over_l);
             if (sp.twmode != TW_NONE) {
-                const uint64_t g = sp.twmode == TW_OFFSET ? uint64_t(off[st])
-                                                          : digit_reverse(uint64_t(blkv[st]), sp.rev);
+                const uint64_t g = sp.twmode == TW_OFFSET ? uint64_t(a.off[st])
+                                                          : digit_reverse(uint64_t(a.blk[st]), sp.rev);
                 apply_stage_twiddle<V, E, P>(v[st], t, g, sp.tw_scale, sp.tt);
             }
             finish_outputs<V, E>(v[st], sp);
 #pragma unroll
-            for (int i = 0; i < E; ++i) dst[base[st] + sp.s * int64_t(t + P * i)] = v[st][i];
+            for (int i = 0; i < E; ++i) dst[a.base[st] + sp.s * int64_t(t + P * i)] = v[st][i];
         }
     } else {
         // outputs land in LDS in natural order; re-read them one contiguous
@@ -327,7 +321,7 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
         __syncthreads();
         const int t2 = tid % P;
         const int c2 = tid / P;
-        const int64_t o2 = tile * LINES + c2;  // one block: line == offset
+        const int64_t o2 = a.tile * LINES + c2;  // one block: line == offset
         const V *row_lds = lds + c2 * PADDED;
         V w[E];
 #pragma unroll
@@ -337,6 +331,73 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
         const int64_t row = sp.row_mul * int64_t(digit_reverse(uint64_t(o2), sp.rev));
 #pragma unroll
         for (int i = 0; i < E; ++i) dst[row + t2 + P * i] = w[i];
+    }
+}
+
+// One pass: each workgroup transforms PIPE tiles of LINES * SETS lines in
+// turn.  Thread (c, t) owns points t + P*i of lines c + LINES*set of a tile:
+// the SETS line sets are loaded together, so a strided tile row is one
+// LINES*SETS-element run, and then transformed one set at a time through the
+// same LDS buffer.  With PIPE > 1 the loads of the next tile are issued
+// before the current tile is transformed, so memory traffic continues while
+// the CU computes.
+template <typename T, int LOGL, int LINES, int SETS, int LAYOUT, int PIPE>
+__global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
+    stage_kernel(StageParams sp)
+{
+    using V = typename vec2<T>::type;
+    constexpr int L = 1 << LOGL;
+    constexpr int E = LineGeom<L>::E;
+    constexpr int P = LineGeom<L>::P;
+    constexpr int PADDED = LineGeom<L>::PADDED;
+    constexpr bool NEED_LDS =
+        (Radices<LOGL>::NSTEPS > 1) || (LAYOUT == LAYOUT_COL2ROW) || (LAYOUT == LAYOUT_ROW2COL);
+    static_assert(LAYOUT != LAYOUT_COL2ROW || SETS == 1, "one line set for row writes");
+    static_assert(LAYOUT != LAYOUT_ROW2COL || SETS == 1, "one line set for column writes");
+    __shared__ V lds[NEED_LDS ? LINES * PADDED : PADDED];
+
+    const int tid = threadIdx.x;
+    int c, t;
+    if constexpr (LAYOUT == LAYOUT_ROW || LAYOUT == LAYOUT_ROW2COL) {
+        t = tid % P;
+        c = tid / P;
+    } else {
+        c = tid % LINES;
+        t = tid / LINES;
+    }
+    const V *src = static_cast<const V *>(sp.src);
+    V *dst = static_cast<V *>(sp.dst);
+
+    // virtual workgroup number of this workgroup's it-th tile: the PIPE tiles
+    // of a workgroup stay on its XCD's run when the grid allows
+    const int64_t groups = sp.ntiles / PIPE;
+    const int64_t bid = blockIdx.x;
+    auto vbid = [&](int it) -> int64_t {
+        if ((groups & 7) == 0) return (bid & 7) + 8 * ((bid >> 3) * PIPE + it);
+        return bid * PIPE + it;
+    };
+
+    V v[SETS][E];
+    TileLines<SETS> a = tile_lines<L, LINES, SETS, LAYOUT>(order_tiles(vbid(0), sp.ntiles, sp.order), c, sp);
+    load_tile<V, E, P, SETS>(v, a, src, t, sp.s);
+#pragma unroll
+    for (int it = 0; it < PIPE; ++it) {
+        V vn[SETS][E];
+        TileLines<SETS> an;
+        if (it + 1 < PIPE) {
+            an = tile_lines<L, LINES, SETS, LAYOUT>(order_tiles(vbid(it + 1), sp.ntiles, sp.order), c, sp);
+            load_tile<V, E, P, SETS>(vn, an, src, t, sp.s);
+        }
+        if (it > 0) __syncthreads();  // the previous tile has finished with LDS
+        process_tile<V, LOGL, LINES, SETS, LAYOUT>(v, a, lds, dst, c, t, tid, sp);
+        if (it + 1 < PIPE) {
+#pragma unroll
+            for (int st = 0; st < SETS; ++st) {
+#pragma unroll
+                for (int i = 0; i < E; ++i) v[st][i] = vn[st][i];
+            }
+            a = an;
+        }
     }
 }
 
@@ -416,14 +477,40 @@ __global__ void twiddle_table_kernel(double2 *lo, int64_t n_lo, double2 *hi, int
 // a plan: the launchers then return success without launching anything.
 thread_local bool g_dry_run = false;
 
+template <typename T, int LOGL, int LINES, int SETS, int LAYOUT, int PIPE>
+static hipError_t launch_pipe(const StageParams &p, hipStream_t stream)
+{
+    constexpr int NT = LINES * LineGeom<(1 << LOGL)>::P;
+    if (p.ntiles % PIPE) return hipErrorInvalidValue;
+    if (g_dry_run) return hipSuccess;
+    hipLaunchKernelGGL((stage_kernel<T, LOGL, LINES, SETS, LAYOUT, PIPE>), dim3(unsigned(p.ntiles / PIPE)),
+                       dim3(NT), 0, stream, p);
+    return hipGetLastError();
+}
+
+// tiles per workgroup (software pipelining depth) of each layout
+#ifndef EFFT_PIPE_COL
+#define EFFT_PIPE_COL 1
+#endif
+#ifndef EFFT_PIPE_ROW
+#define EFFT_PIPE_ROW 1
+#endif
+#ifndef EFFT_PIPE_X
+#define EFFT_PIPE_X 2
+#endif
+
 template <typename T, int LOGL, int LINES, int SETS, int LAYOUT>
 static hipError_t launch_one(const StageParams &p, hipStream_t stream)
 {
-    constexpr int NT = LINES * LineGeom<(1 << LOGL)>::P;
-    if (g_dry_run) return hipSuccess;
-    hipLaunchKernelGGL((stage_kernel<T, LOGL, LINES, SETS, LAYOUT>), dim3(unsigned(p.ntiles)), dim3(NT),
-                       0, stream, p);
-    return hipGetLastError();
+    // a second tile in flight costs one more tile of registers: only
+    // workgroups of at most 512 threads (256-VGPR budget) have room
+    constexpr bool ROOM = SETS == 1 && LINES * LineGeom<(1 << LOGL)>::P <= 512;
+    constexpr int PIPE = !ROOM ? 1
+                         : (LAYOUT == LAYOUT_COL) ? EFFT_PIPE_COL
+                         : (LAYOUT == LAYOUT_ROW) ? EFFT_PIPE_ROW : EFFT_PIPE_X;
+    if (PIPE > 1 && p.ntiles >= 64 * PIPE && p.ntiles % PIPE == 0)
+        return launch_pipe<T, LOGL, LINES, SETS, LAYOUT, PIPE>(p, stream);
+    return launch_pipe<T, LOGL, LINES, SETS, LAYOUT, 1>(p, stream);
 }
 
 // row layout: workgroups of about 256 threads, or one line when fewer exist
