@@ -111,15 +111,35 @@ void set_dry_run(bool on);
 // LDS budget of one workgroup tile (one workgroup per CU on gfx950's 160 KB)
 constexpr int TILE_LDS_BYTES = 143360;
 
+// Points per thread of the strided layouts.  Setting EFFT_C64_COL_POINTS to
+// 32 gives complex64 lines of 256 points or more half the threads; measured on
+// gfx950 it was no faster (within 2%), and its second line set or prefetched
+// tile spills registers, so the default is 16 everywhere.
+#ifndef EFFT_C64_COL_POINTS
+#define EFFT_C64_COL_POINTS 16
+#endif
+__host__ __device__ constexpr int col_points(int dtype_bytes, int logl)
+{
+    return (dtype_bytes == 8 && logl >= 8) ? EFFT_C64_COL_POINTS : 16;
+}
+
+// threads per line of L = 2^logl points at ep points per thread
+__host__ __device__ constexpr int line_threads(int logl, int ep)
+{
+    return (1 << logl) >= ep ? (1 << logl) / ep : 1;
+}
+
 // Lines per workgroup set of the strided layouts when the tile is made as
-// wide as the LDS budget and 1024 threads allow: each tile row is then one
-// long contiguous run.  Shorter lines get wider tiles.
+// wide as the LDS budget and the thread budget (1024, or 512 at 32 points per
+// thread) allow: each tile row is then one long contiguous run.  Shorter
+// lines get wider tiles.
 __host__ __device__ constexpr int col_lines_max(int dtype_bytes, int logl)
 {
     const int l = 1 << logl;
-    const int p = logl >= 4 ? l / 16 : 1;
+    const int ep = col_points(dtype_bytes, logl);
+    const int p = line_threads(logl, ep);
     const int padded = l + (l >> 4) + 2;
-    int w = 1024 / p;
+    int w = (ep == 32 ? 512 : 1024) / p;
     while (w > 1 && w * padded * dtype_bytes > TILE_LDS_BYTES) w >>= 1;
     if (w > 256) w = 256;
     return w;
@@ -145,17 +165,18 @@ inline int col_lines(int dtype_bytes, int logl, int64_t stride, bool same_positi
     return col_lines_min(dtype_bytes);
 }
 
-// Line sets per workgroup of LAYOUT_COL passes: where even the widest tile is
-// a single 128-byte segment (complex128 lines of 1024 points), a second set
-// loaded together makes each tile row a 256-byte run at large strides; the
-// register file has room for it with 512 threads.
+// Line sets per workgroup of LAYOUT_COL passes: where even the widest tile of
+// 1024-point complex128 lines is a single 128-byte segment (8 lines), a second
+// set loaded together makes each tile row a 256-byte run at large strides; the
+// register file has room for it with 512 threads (not for complex64 tiles,
+// whose second set spills).
 #ifndef EFFT_COL_SETS
 #define EFFT_COL_SETS 2
 #endif
 inline int col_sets(int dtype_bytes, int logl, int lines, int64_t stride)
 {
-    return (EFFT_COL_SETS >= 2 && dtype_bytes == 16 && col_lines_max(dtype_bytes, logl) == 8 &&
-            lines == 8 && stride >= (int64_t(1) << 16))
+    return (EFFT_COL_SETS >= 2 && dtype_bytes == 16 && logl == 10 && lines == col_lines_max(dtype_bytes, logl) &&
+            lines * dtype_bytes == 128 && stride >= (int64_t(1) << 16))
                ? 2
                : 1;
 }

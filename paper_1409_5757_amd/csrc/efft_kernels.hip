@@ -23,8 +23,8 @@ namespace efft {
 // power-of-two strides of the Stockham writes across banks
 __device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
 
-template <int L> struct LineGeom {
-    static constexpr int E = L >= 16 ? 16 : L;  // points per thread
+template <int L, int EP = 16> struct LineGeom {
+    static constexpr int E = L >= EP ? EP : L;  // points per thread
     static constexpr int P = L / E;             // threads per line
     static constexpr int PADDED = L + (L >> 4) + 2;  // padded line stride in LDS
 };
@@ -81,12 +81,12 @@ __device__ __forceinline__ void twiddle_line(V *u, double2 w)
 // twiddle W_{NS*R}^{(j mod NS)*r} and an R-point DFT, output r goes to line
 // position (j/NS)*NS*R + (j mod NS) + NS*r -- into LDS, or, on the last step
 // (where that position is j + (L/R)*r), back into register b + (E/R)*r.
-template <typename V, int L, int R, int NS, bool TO_LDS>
+template <typename V, int L, int R, int NS, bool TO_LDS, int EP>
 __device__ __forceinline__ void stockham_step(V *v, V *lds_line, int t, const TwTable &tt,
                                               uint64_t n_over_l)
 {
-    constexpr int E = LineGeom<L>::E;
-    constexpr int P = LineGeom<L>::P;
+    constexpr int E = LineGeom<L, EP>::E;
+    constexpr int P = LineGeom<L, EP>::P;
     constexpr int NB = E / R;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -112,11 +112,11 @@ __device__ __forceinline__ void stockham_step(V *v, V *lds_line, int t, const Tw
     }
 }
 
-template <typename V, int L>
+template <typename V, int L, int EP>
 __device__ __forceinline__ void lds_gather(V *v, const V *lds_line, int t)
 {
-    constexpr int E = LineGeom<L>::E;
-    constexpr int P = LineGeom<L>::P;
+    constexpr int E = LineGeom<L, EP>::E;
+    constexpr int P = LineGeom<L, EP>::P;
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = lds_line[lds_pad(t + P * i)];
 }
@@ -124,7 +124,7 @@ __device__ __forceinline__ void lds_gather(V *v, const V *lds_line, int t)
 // All Stockham steps of a line of 2^LOGL points.  On entry v holds input
 // points t + P*i; on exit outputs k = t + P*i (FINAL_TO_LDS: the outputs are
 // left in LDS at natural positions instead).
-template <typename V, int LOGL, bool FINAL_TO_LDS>
+template <typename V, int LOGL, bool FINAL_TO_LDS, int EP>
 __device__ __forceinline__ void line_fft(V *v, V *lds_line, int t, const TwTable &tt,
                                          uint64_t n_over_l)
 {
@@ -134,29 +134,29 @@ __device__ __forceinline__ void line_fft(V *v, V *lds_line, int t, const TwTable
     static_assert(NST <= 4, "line too long");
     // step 0
     if constexpr (NST == 1) {
-        stockham_step<V, L, Rd::radix(0), 1, FINAL_TO_LDS>(v, lds_line, t, tt, n_over_l);
+        stockham_step<V, L, Rd::radix(0), 1, FINAL_TO_LDS, EP>(v, lds_line, t, tt, n_over_l);
         return;
     } else {
-        stockham_step<V, L, Rd::radix(0), 1, true>(v, lds_line, t, tt, n_over_l);
+        stockham_step<V, L, Rd::radix(0), 1, true, EP>(v, lds_line, t, tt, n_over_l);
         __syncthreads();
-        lds_gather<V, L>(v, lds_line, t);
+        lds_gather<V, L, EP>(v, lds_line, t);
         __syncthreads();
         if constexpr (NST == 2) {
-            stockham_step<V, L, Rd::radix(1), Rd::span(1), FINAL_TO_LDS>(v, lds_line, t, tt, n_over_l);
+            stockham_step<V, L, Rd::radix(1), Rd::span(1), FINAL_TO_LDS, EP>(v, lds_line, t, tt, n_over_l);
         } else {
-            stockham_step<V, L, Rd::radix(1), Rd::span(1), true>(v, lds_line, t, tt, n_over_l);
+            stockham_step<V, L, Rd::radix(1), Rd::span(1), true, EP>(v, lds_line, t, tt, n_over_l);
             __syncthreads();
-            lds_gather<V, L>(v, lds_line, t);
+            lds_gather<V, L, EP>(v, lds_line, t);
             __syncthreads();
             if constexpr (NST == 3) {
-                stockham_step<V, L, Rd::radix(2), Rd::span(2), FINAL_TO_LDS>(v, lds_line, t, tt,
+                stockham_step<V, L, Rd::radix(2), Rd::span(2), FINAL_TO_LDS, EP>(v, lds_line, t, tt,
                                                                              n_over_l);
             } else {
-                stockham_step<V, L, Rd::radix(2), Rd::span(2), true>(v, lds_line, t, tt, n_over_l);
+                stockham_step<V, L, Rd::radix(2), Rd::span(2), true, EP>(v, lds_line, t, tt, n_over_l);
                 __syncthreads();
-                lds_gather<V, L>(v, lds_line, t);
+                lds_gather<V, L, EP>(v, lds_line, t);
                 __syncthreads();
-                stockham_step<V, L, Rd::radix(3), Rd::span(3), FINAL_TO_LDS>(v, lds_line, t, tt,
+                stockham_step<V, L, Rd::radix(3), Rd::span(3), FINAL_TO_LDS, EP>(v, lds_line, t, tt,
                                                                              n_over_l);
             }
         }
@@ -164,8 +164,9 @@ __device__ __forceinline__ void line_fft(V *v, V *lds_line, int t, const TwTable
 }
 
 // Multiply v[i] (output k = t + P*i of a line) by W_N^(g*k*scale): two table
-// lookups, then W^(g*scale*(t + P*(4a + b))) = c_a * s^b with c_a = w0 * s^(4a),
-// s = W^(g*scale*P), all in FP64 and rounded once to the storage type.
+// lookups, then W^(g*scale*(t + P*(4a + b))) = c_a * s^b with c_a = w0 * s^(4a)
+// (c_{a+1} = c_a * s^4), s = W^(g*scale*P), all in FP64 and rounded once to
+// the storage type.
 template <typename V, int E, int P>
 __device__ __forceinline__ void apply_stage_twiddle(V *v, int t, uint64_t g, uint64_t scale,
                                                     const TwTable &tt)
@@ -179,12 +180,10 @@ __device__ __forceinline__ void apply_stage_twiddle(V *v, int t, uint64_t g, uin
         const double2 s2 = cmul(s1, s1);
         const double2 s3 = cmul(s2, s1);
         const double2 s4 = cmul(s2, s2);
+        double2 c = w0;
 #pragma unroll
         for (int a = 0; a < (E + 3) / 4; ++a) {
-            double2 c = w0;
-            if (a == 1) c = cmul(w0, s4);
-            if (a == 2) c = cmul(w0, cmul(s4, s4));
-            if (a == 3) c = cmul(cmul(w0, s4), cmul(s4, s4));
+            if (a > 0) c = cmul(c, s4);
 #pragma unroll
             for (int b = 0; b < 4 && 4 * a + b < E; ++b) {
                 const int i = 4 * a + b;
@@ -268,14 +267,14 @@ __device__ __forceinline__ void load_tile(V (&v)[SETS][E], const TileLines<SETS>
 }
 
 // Transform the loaded tile and store it (the layout decides where).
-template <typename V, int LOGL, int LINES, int SETS, int LAYOUT>
-__device__ __forceinline__ void process_tile(V (&v)[SETS][LineGeom<(1 << LOGL)>::E], const TileLines<SETS> &a,
-                                             V *lds, V *dst, int c, int t, int tid, const StageParams &sp)
+template <typename V, int LOGL, int LINES, int SETS, int LAYOUT, int EP, int E>
+__device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SETS> &a, V *lds, V *dst,
+                                             int c, int t, int tid, const StageParams &sp)
 {
     constexpr int L = 1 << LOGL;
-    constexpr int E = LineGeom<L>::E;
-    constexpr int P = LineGeom<L>::P;
-    constexpr int PADDED = LineGeom<L>::PADDED;
+    static_assert(E == LineGeom<L, EP>::E, "points per thread");
+    constexpr int P = LineGeom<L, EP>::P;
+    constexpr int PADDED = LineGeom<L, EP>::PADDED;
     if (sp.conj) {
 #pragma unroll
         for (int st = 0; st < SETS; ++st) {
@@ -288,7 +287,7 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][LineGeom<(1 << LOGL)>:
         // outputs land in LDS in natural order; re-read them across the tile's
         // lines (lane = line) and write output k of column `line` at
         // line + row_mul * k, so each store covers LINES consecutive elements
-        line_fft<V, LOGL, true>(v[0], lds_line, t, sp.tt, sp.n_over_l);
+        line_fft<V, LOGL, true, EP>(v[0], lds_line, t, sp.tt, sp.n_over_l);
         __syncthreads();
         const int c2 = tid % LINES;
         const int t2 = tid / LINES;
@@ -304,7 +303,7 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][LineGeom<(1 << LOGL)>:
 #pragma unroll
         for (int st = 0; st < SETS; ++st) {
             if (st > 0) __syncthreads();  // the previous set has finished with LDS
-            line_fft<V, LOGL, false>(v[st], lds_line, t, sp.tt, sp.n_over_l);
+            line_fft<V, LOGL, false, EP>(v[st], lds_line, t, sp.tt, sp.n_over_l);
             if (sp.twmode != TW_NONE) {
                 const uint64_t g = sp.twmode == TW_OFFSET ? uint64_t(a.off[st])
                                                           : digit_reverse(uint64_t(a.blk[st]), sp.rev);
@@ -317,7 +316,7 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][LineGeom<(1 << LOGL)>:
     } else {
         // outputs land in LDS in natural order; re-read them one contiguous
         // row per line and write that row at its digit-reversed position
-        line_fft<V, LOGL, true>(v[0], lds_line, t, sp.tt, sp.n_over_l);
+        line_fft<V, LOGL, true, EP>(v[0], lds_line, t, sp.tt, sp.n_over_l);
         __syncthreads();
         const int t2 = tid % P;
         const int c2 = tid / P;
@@ -341,15 +340,20 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][LineGeom<(1 << LOGL)>:
 // same LDS buffer.  With PIPE > 1 the loads of the next tile are issued
 // before the current tile is transformed, so memory traffic continues while
 // the CU computes.
-template <typename T, int LOGL, int LINES, int SETS, int LAYOUT, int PIPE>
-__global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
+template <int LOGL, int LINES, int EP> constexpr int stage_threads()
+{
+    return LINES * LineGeom<(1 << LOGL), EP>::P;
+}
+
+template <typename T, int LOGL, int LINES, int SETS, int LAYOUT, int PIPE, int EP>
+__global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()))
     stage_kernel(StageParams sp)
 {
     using V = typename vec2<T>::type;
     constexpr int L = 1 << LOGL;
-    constexpr int E = LineGeom<L>::E;
-    constexpr int P = LineGeom<L>::P;
-    constexpr int PADDED = LineGeom<L>::PADDED;
+    constexpr int E = LineGeom<L, EP>::E;
+    constexpr int P = LineGeom<L, EP>::P;
+    constexpr int PADDED = LineGeom<L, EP>::PADDED;
     constexpr bool NEED_LDS =
         (Radices<LOGL>::NSTEPS > 1) || (LAYOUT == LAYOUT_COL2ROW) || (LAYOUT == LAYOUT_ROW2COL);
     static_assert(LAYOUT != LAYOUT_COL2ROW || SETS == 1, "one line set for row writes");
@@ -389,7 +393,7 @@ __global__ void __launch_bounds__(LINES *LineGeom<(1 << LOGL)>::P)
             load_tile<V, E, P, SETS>(vn, an, src, t, sp.s);
         }
         if (it > 0) __syncthreads();  // the previous tile has finished with LDS
-        process_tile<V, LOGL, LINES, SETS, LAYOUT>(v, a, lds, dst, c, t, tid, sp);
+        process_tile<V, LOGL, LINES, SETS, LAYOUT, EP>(v, a, lds, dst, c, t, tid, sp);
         if (it + 1 < PIPE) {
 #pragma unroll
             for (int st = 0; st < SETS; ++st) {
@@ -477,13 +481,13 @@ __global__ void twiddle_table_kernel(double2 *lo, int64_t n_lo, double2 *hi, int
 // a plan: the launchers then return success without launching anything.
 thread_local bool g_dry_run = false;
 
-template <typename T, int LOGL, int LINES, int SETS, int LAYOUT, int PIPE>
+template <typename T, int LOGL, int LINES, int SETS, int LAYOUT, int PIPE, int EP>
 static hipError_t launch_pipe(const StageParams &p, hipStream_t stream)
 {
-    constexpr int NT = LINES * LineGeom<(1 << LOGL)>::P;
+    constexpr int NT = LINES * LineGeom<(1 << LOGL), EP>::P;
     if (p.ntiles % PIPE) return hipErrorInvalidValue;
     if (g_dry_run) return hipSuccess;
-    hipLaunchKernelGGL((stage_kernel<T, LOGL, LINES, SETS, LAYOUT, PIPE>), dim3(unsigned(p.ntiles / PIPE)),
+    hipLaunchKernelGGL((stage_kernel<T, LOGL, LINES, SETS, LAYOUT, PIPE, EP>), dim3(unsigned(p.ntiles / PIPE)),
                        dim3(NT), 0, stream, p);
     return hipGetLastError();
 }
@@ -499,18 +503,18 @@ static hipError_t launch_pipe(const StageParams &p, hipStream_t stream)
 #define EFFT_PIPE_X 2
 #endif
 
-template <typename T, int LOGL, int LINES, int SETS, int LAYOUT>
+template <typename T, int LOGL, int LINES, int SETS, int LAYOUT, int EP = 16>
 static hipError_t launch_one(const StageParams &p, hipStream_t stream)
 {
     // a second tile in flight costs one more tile of registers: only
-    // workgroups of at most 512 threads (256-VGPR budget) have room
-    constexpr bool ROOM = SETS == 1 && LINES * LineGeom<(1 << LOGL)>::P <= 512;
+    // workgroups of at most 512 threads at 16 points per thread have room
+    constexpr bool ROOM = SETS == 1 && EP == 16 && LINES * LineGeom<(1 << LOGL), EP>::P <= 512;
     constexpr int PIPE = !ROOM ? 1
                          : (LAYOUT == LAYOUT_COL) ? EFFT_PIPE_COL
                          : (LAYOUT == LAYOUT_ROW) ? EFFT_PIPE_ROW : EFFT_PIPE_X;
     if (PIPE > 1 && p.ntiles >= 64 * PIPE && p.ntiles % PIPE == 0)
-        return launch_pipe<T, LOGL, LINES, SETS, LAYOUT, PIPE>(p, stream);
-    return launch_pipe<T, LOGL, LINES, SETS, LAYOUT, 1>(p, stream);
+        return launch_pipe<T, LOGL, LINES, SETS, LAYOUT, PIPE, EP>(p, stream);
+    return launch_pipe<T, LOGL, LINES, SETS, LAYOUT, 1, EP>(p, stream);
 }
 
 // row layout: workgroups of about 256 threads, or one line when fewer exist
@@ -526,10 +530,12 @@ template <typename T, int LOGL>
 static hipError_t dispatch_logl(int layout, int lines, int sets, const StageParams &p,
                                 hipStream_t stream)
 {
+    constexpr int EB = int(2 * sizeof(T));
     constexpr int P = LineGeom<(1 << LOGL)>::P;
     constexpr int ROWW = P >= 256 ? 1 : 256 / P;
-    constexpr int WMAX = col_lines_max(int(2 * sizeof(T)), LOGL);
-    constexpr int WMIN = col_lines_min(int(2 * sizeof(T)));
+    constexpr int EPC = col_points(EB, LOGL);
+    constexpr int WMAX = col_lines_max(EB, LOGL);
+    constexpr int WMIN = col_lines_min(EB);
     if (layout == LAYOUT_ROW) {
         if (sets != 1) return hipErrorInvalidValue;
         if (lines == ROWW) return launch_one<T, LOGL, ROWW, 1, LAYOUT_ROW>(p, stream);
@@ -538,24 +544,24 @@ static hipError_t dispatch_logl(int layout, int lines, int sets, const StagePara
     }
     if constexpr (LOGL >= 4 && LOGL <= 10) {
         if (layout == LAYOUT_COL) {
-            if (lines == WMAX && sets == 1) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL>(p, stream);
-            if constexpr (WMAX == 8) {
-                if (lines == WMAX && sets == 2) return launch_one<T, LOGL, WMAX, 2, LAYOUT_COL>(p, stream);
+            if (lines == WMAX && sets == 1) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL, EPC>(p, stream);
+            if constexpr (LOGL == 10 && WMAX * EB == 128) {
+                if (lines == WMAX && sets == 2) return launch_one<T, LOGL, WMAX, 2, LAYOUT_COL, EPC>(p, stream);
             }
             if constexpr (WMIN != WMAX) {
-                if (lines == WMIN && sets == 1) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL>(p, stream);
+                if (lines == WMIN && sets == 1) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL, EPC>(p, stream);
             }
         }
         if (layout == LAYOUT_COL2ROW && sets == 1) {
-            if (lines == WMAX) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL2ROW>(p, stream);
+            if (lines == WMAX) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL2ROW, EPC>(p, stream);
             if constexpr (WMIN != WMAX) {
-                if (lines == WMIN) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL2ROW>(p, stream);
+                if (lines == WMIN) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL2ROW, EPC>(p, stream);
             }
         }
         if (layout == LAYOUT_ROW2COL && sets == 1) {
-            if (lines == WMAX) return launch_one<T, LOGL, WMAX, 1, LAYOUT_ROW2COL>(p, stream);
+            if (lines == WMAX) return launch_one<T, LOGL, WMAX, 1, LAYOUT_ROW2COL, EPC>(p, stream);
             if constexpr (WMIN != WMAX) {
-                if (lines == WMIN) return launch_one<T, LOGL, WMIN, 1, LAYOUT_ROW2COL>(p, stream);
+                if (lines == WMIN) return launch_one<T, LOGL, WMIN, 1, LAYOUT_ROW2COL, EPC>(p, stream);
             }
         }
     }
