@@ -17,9 +17,12 @@ template <> struct vec2<float> { using type = float2; };
 
 template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
 template <typename V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
+// Complex product with its fused multiply-adds spelled out, so every kernel
+// variant rounds each product identically (the compiler may not re-contract
+// it differently from one instantiation to the next).
 template <typename V> __device__ __forceinline__ V cmul(V a, V b)
 {
-    return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    return V{fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
 }
 template <typename V> __device__ __forceinline__ V cconj(V a) { return V{a.x, -a.y}; }
 // multiply by -i = exp(-i*pi/2), the forward quarter-turn root
@@ -131,15 +134,6 @@ __device__ __forceinline__ double2 tw_lookup(const TwTable &tt, uint64_t m)
     const double2 a = tt.hi[m >> tt.h];
     const double2 b = tt.lo[m & tt.mask_lo];
     return cmul(a, b);
-}
-
-// p[r] = w^r for r < NP, balanced products so w^r takes ceil(log2 r) roundings
-template <int NP> __device__ __forceinline__ void powers(double2 w, double2 *p)
-{
-    p[0] = double2{1.0, 0.0};
-    if constexpr (NP > 1) p[1] = w;
-#pragma unroll
-    for (int r = 2; r < NP; ++r) p[r] = cmul(p[r / 2], p[r - r / 2]);
 }
 
 template <typename V> __device__ __forceinline__ V round_tw(double2 w)
