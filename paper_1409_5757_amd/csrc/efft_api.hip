@@ -199,6 +199,16 @@ void apply_scale_to_last(std::vector<Pass> &v, double scale)
     }
 }
 
+void set_hints(std::vector<Pass> &v)
+{
+    for (Pass &ps : v) {
+        if (ps.swap)
+            ps.wp.nt_hint = EFFT_NT_SWAP;
+        else
+            set_stream_hints(ps.sp, ps.layout);
+    }
+}
+
 void build_passes(efft_plan_s *p, const TwTable &tt)
 {
     build_passes_unscaled(p, tt);
@@ -213,6 +223,8 @@ void build_passes(efft_plan_s *p, const TwTable &tt)
         build_scratch_passes(p, tt);
         apply_scale_to_last(p->scratch_passes, p->scale);
     }
+    set_hints(p->passes);
+    set_hints(p->scratch_passes);
 }
 
 // Scratch schedule of an in-place plan: the sub-FFT passes of digits

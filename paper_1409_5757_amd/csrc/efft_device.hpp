@@ -118,6 +118,25 @@ template <int R, typename V> __device__ __forceinline__ void dft(V *v)
     else static_assert(R == 1, "unsupported radix");
 }
 
+// Loads and stores with the non-temporal hint: the data of a pass is touched
+// once, so it is streamed past the caches instead of displacing what is
+// reused there (twiddle tables, lines of tiles still in flight).
+template <typename V> __device__ __forceinline__ V load_nt(const V *p)
+{
+    using T = decltype(V{}.x);
+    typedef T native2 __attribute__((ext_vector_type(2)));
+    const native2 r = __builtin_nontemporal_load(reinterpret_cast<const native2 *>(p));
+    return V{r.x, r.y};
+}
+
+template <typename V> __device__ __forceinline__ void store_nt(V *p, V v)
+{
+    using T = decltype(V{}.x);
+    typedef T native2 __attribute__((ext_vector_type(2)));
+    const native2 r = {v.x, v.y};
+    __builtin_nontemporal_store(r, reinterpret_cast<native2 *>(p));
+}
+
 // ---------------------------------------------------------------- twiddles
 // Two-level FP64 table of W_N^m = exp(-2*pi*i*m/N): W_N^m = hi[m >> h] * lo[m & (2^h - 1)].
 struct TwTable {

@@ -257,12 +257,33 @@ __device__ __forceinline__ TileLines<SETS> tile_lines(int64_t tile, int c, const
 
 template <typename V, int E, int P, int SETS>
 __device__ __forceinline__ void load_tile(V (&v)[SETS][E], const TileLines<SETS> &a, const V *src, int t,
-                                          int64_t s)
+                                          int64_t s, int nt)
 {
+    if (nt) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
+        for (int i = 0; i < E; ++i) {
 #pragma unroll
-        for (int st = 0; st < SETS; ++st) v[st][i] = src[a.base[st] + s * int64_t(t + P * i)];
+            for (int st = 0; st < SETS; ++st) v[st][i] = load_nt(src + a.base[st] + s * int64_t(t + P * i));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+#pragma unroll
+            for (int st = 0; st < SETS; ++st) v[st][i] = src[a.base[st] + s * int64_t(t + P * i)];
+        }
+    }
+}
+
+// Stores of E points of a thread, point i at p + stride * i.
+template <typename V, int E>
+__device__ __forceinline__ void store_points(V *p, int64_t stride, const V *w, int nt)
+{
+    if (nt) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) store_nt(p + stride * i, w[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i) p[stride * i] = w[i];
     }
 }
 
@@ -297,8 +318,7 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
 #pragma unroll
         for (int i = 0; i < E; ++i) w[i] = col_lds[lds_pad(t2 + P * i)];
         finish_outputs<V, E>(w, sp);
-#pragma unroll
-        for (int i = 0; i < E; ++i) dst[col + sp.row_mul * int64_t(t2 + P * i)] = w[i];
+        store_points<V, E>(dst + col + sp.row_mul * int64_t(t2), sp.row_mul * int64_t(P), w, sp.nt_store);
     } else if constexpr (LAYOUT != LAYOUT_COL2ROW) {
 #pragma unroll
         for (int st = 0; st < SETS; ++st) {
@@ -310,8 +330,7 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
                 apply_stage_twiddle<V, E, P>(v[st], t, g, sp.tw_scale, sp.tt);
             }
             finish_outputs<V, E>(v[st], sp);
-#pragma unroll
-            for (int i = 0; i < E; ++i) dst[a.base[st] + sp.s * int64_t(t + P * i)] = v[st][i];
+            store_points<V, E>(dst + a.base[st] + sp.s * int64_t(t), sp.s * int64_t(P), v[st], sp.nt_store);
         }
     } else {
         // outputs land in LDS in natural order; re-read them one contiguous
@@ -328,8 +347,7 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
         apply_stage_twiddle<V, E, P>(w, t2, uint64_t(o2), sp.tw_scale, sp.tt);
         finish_outputs<V, E>(w, sp);
         const int64_t row = sp.row_mul * int64_t(digit_reverse(uint64_t(o2), sp.rev));
-#pragma unroll
-        for (int i = 0; i < E; ++i) dst[row + t2 + P * i] = w[i];
+        store_points<V, E>(dst + row + t2, int64_t(P), w, sp.nt_store);
     }
 }
 
@@ -383,14 +401,14 @@ __global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()))
 
     V v[SETS][E];
     TileLines<SETS> a = tile_lines<L, LINES, SETS, LAYOUT>(order_tiles(vbid(0), sp.ntiles, sp.order), c, sp);
-    load_tile<V, E, P, SETS>(v, a, src, t, sp.s);
+    load_tile<V, E, P, SETS>(v, a, src, t, sp.s, sp.nt_load);
 #pragma unroll
     for (int it = 0; it < PIPE; ++it) {
         V vn[SETS][E];
         TileLines<SETS> an;
         if (it + 1 < PIPE) {
             an = tile_lines<L, LINES, SETS, LAYOUT>(order_tiles(vbid(it + 1), sp.ntiles, sp.order), c, sp);
-            load_tile<V, E, P, SETS>(vn, an, src, t, sp.s);
+            load_tile<V, E, P, SETS>(vn, an, src, t, sp.s, sp.nt_load);
         }
         if (it > 0) __syncthreads();  // the previous tile has finished with LDS
         process_tile<V, LOGL, LINES, SETS, LAYOUT, EP>(v, a, lds, dst, c, t, tid, sp);
@@ -411,7 +429,7 @@ __global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()))
 // Each unordered pair is handled by the workgroup whose key is the smaller;
 // a tile paired with itself is transposed in place.  Every element is read
 // and written exactly once.
-template <typename T, int TS, int NT>
+template <typename T, int TS, int NT, bool STREAM>
 __global__ void __launch_bounds__(NT) swap_kernel(SwapParams p)
 {
     using V = typename vec2<T>::type;
@@ -437,21 +455,29 @@ __global__ void __launch_bounds__(NT) swap_kernel(SwapParams p)
     const int64_t rowA = p.M * p.R;  // stride between consecutive outer rows
     const int64_t baseA = (I * TS * p.M + mu) * p.R + J * TS;
     const int64_t baseB = (J * TS * p.M + rmu) * p.R + I * TS;
+    auto ld = [&](int64_t i) {
+        if constexpr (STREAM) return load_nt(x + i);
+        else return x[i];
+    };
+    auto st = [&](int64_t i, V v) {
+        if constexpr (STREAM) store_nt(x + i, v);
+        else x[i] = v;
+    };
 #pragma unroll
-    for (int a = r0; a < TS; a += ROWS_PER_PASS) ta[a][col] = x[baseA + a * rowA + col];
+    for (int a = r0; a < TS; a += ROWS_PER_PASS) ta[a][col] = ld(baseA + a * rowA + col);
     if (!self) {
 #pragma unroll
-        for (int a = r0; a < TS; a += ROWS_PER_PASS) tb[a][col] = x[baseB + a * rowA + col];
+        for (int a = r0; a < TS; a += ROWS_PER_PASS) tb[a][col] = ld(baseB + a * rowA + col);
     }
     __syncthreads();
     if (self) {
 #pragma unroll
-        for (int a = r0; a < TS; a += ROWS_PER_PASS) x[baseA + a * rowA + col] = ta[col][a];
+        for (int a = r0; a < TS; a += ROWS_PER_PASS) st(baseA + a * rowA + col, ta[col][a]);
     } else {
 #pragma unroll
         for (int a = r0; a < TS; a += ROWS_PER_PASS) {
-            x[baseB + a * rowA + col] = ta[col][a];
-            x[baseA + a * rowA + col] = tb[col][a];
+            st(baseB + a * rowA + col, ta[col][a]);
+            st(baseA + a * rowA + col, tb[col][a]);
         }
     }
 }
@@ -545,7 +571,7 @@ static hipError_t dispatch_logl(int layout, int lines, int sets, const StagePara
     if constexpr (LOGL >= 4 && LOGL <= 10) {
         if (layout == LAYOUT_COL) {
             if (lines == WMAX && sets == 1) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL, EPC>(p, stream);
-            if constexpr (LOGL == 10 && WMAX * EB == 128) {
+            if constexpr (LOGL == 10 && EB == 16 && WMAX * EB == 128) {
                 if (lines == WMAX && sets == 2) return launch_one<T, LOGL, WMAX, 2, LAYOUT_COL, EPC>(p, stream);
             }
             if constexpr (WMIN != WMAX) {
@@ -603,11 +629,14 @@ hipError_t launch_swap(int dtype_bytes, const SwapParams &p, hipStream_t stream)
     const int64_t ts = p.R / p.nt;
     if (p.M > (int64_t(1) << 24) || p.nt * p.nt > 65535) return hipErrorInvalidValue;
     const dim3 grid(unsigned(p.M), unsigned(p.nt * p.nt));
-#define EFFT_SWAP(T, TSV, NTV)                                                        \
-    if (ts == TSV) {                                                                  \
-        if (g_dry_run) return hipSuccess;                                             \
-        hipLaunchKernelGGL((swap_kernel<T, TSV, NTV>), grid, dim3(NTV), 0, stream, p); \
-        return hipGetLastError();                                                     \
+#define EFFT_SWAP(T, TSV, NTV)                                                                      \
+    if (ts == TSV) {                                                                                \
+        if (g_dry_run) return hipSuccess;                                                           \
+        if (p.nt_hint)                                                                              \
+            hipLaunchKernelGGL((swap_kernel<T, TSV, NTV, true>), grid, dim3(NTV), 0, stream, p);    \
+        else                                                                                        \
+            hipLaunchKernelGGL((swap_kernel<T, TSV, NTV, false>), grid, dim3(NTV), 0, stream, p);   \
+        return hipGetLastError();                                                                   \
     }
     if (dtype_bytes == 16) {
         EFFT_SWAP(double, 64, 512)
