@@ -99,6 +99,22 @@ efft_plan_t *efft_plan(int64_t n, int dtype, int dir, int inplace);
 efft_plan_t *efft_plan_scaled(int64_t n, int dtype, int dir, int inplace, double scale);
 
 /*
+ * Batched plan: `batch` independent transforms of n points each (the paper's
+ * "many transforms" mode, Section 2.1), signal b at elements
+ * [b*n, (b+1)*n) of every array the exec calls take; each exec call then
+ * transforms all of them with the same number of passes as one signal.
+ * n, dtype, dir, inplace and scale as for efft_plan_scaled; batch >= 1 (else
+ * EFFT_ERR_ARG) and batch * n <= 2^40 (else EFFT_ERR_SIZE).  A scratch array
+ * for efft_exec_scratch then holds batch * n elements.  efft_plan_scaled is
+ * efft_plan_many with batch = 1.
+ */
+efft_plan_t *efft_plan_many(int64_t n, int64_t batch, int dtype, int dir, int inplace, double scale);
+
+/* Signals per execution of a plan (1 unless made by efft_plan_many); -1 if
+ * plan is not a live plan. */
+int64_t efft_plan_batch(const efft_plan_t *plan);
+
+/*
  * Real-data plan for N = 2^q real samples (1 <= q <= 34), always out of
  * place, executed with efft_exec_oop.  The paper's EFFT transforms real data
  * (Section 2.1 "code:dfti", Section 4); this keeps the standard half-spectrum

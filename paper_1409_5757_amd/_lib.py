@@ -39,6 +39,10 @@ def _bind(lib):
     lib.efft_plan.restype = vp
     lib.efft_plan_scaled.argtypes = [i64, ci, ci, ci, ctypes.c_double]
     lib.efft_plan_scaled.restype = vp
+    lib.efft_plan_many.argtypes = [i64, i64, ci, ci, ci, ctypes.c_double]
+    lib.efft_plan_many.restype = vp
+    lib.efft_plan_batch.argtypes = [vp]
+    lib.efft_plan_batch.restype = i64
     lib.efft_plan_real.argtypes = [i64, ci, ci, ctypes.c_double]
     lib.efft_plan_real.restype = vp
     lib.efft_exec.argtypes = [vp, vp, vp]

@@ -10,8 +10,9 @@
 
 Inputs are complex64 / complex128 CUDA tensors whose last dimension is a
 power of two (N = 2^q, q <= 34).  Leading dimensions are a batch of
-independent transforms.  All work runs in ``libefft.so`` on the tensor's
-device, on the current torch stream; there is no CPU fallback.
+independent transforms, done by one batched plan (every pass of the
+transform covers all rows at once).  All work runs in ``libefft.so`` on the
+tensor's device, on the current torch stream; there is no CPU fallback.
 
 ``EfftFFT`` is the differentiable form: for the C-linear map y = s * A x its
 backward applies s * A^H, the transform of the opposite direction with the
@@ -32,14 +33,16 @@ _DTYPES = {torch.complex64: EFFT_C64, torch.complex128: EFFT_C128}
 
 
 class Plan:
-    """One committed transform (size, dtype, direction, in/out of place, scale)."""
+    """One committed transform (size, batch, dtype, direction, in/out of place,
+    scale).  Each execution transforms ``batch`` contiguous signals of n points."""
 
     def __init__(self, n: int, dtype: torch.dtype, direction: int = EFFT_FORWARD,
-                 inplace: bool = False, scale: float = 1.0, device=None):
+                 inplace: bool = False, scale: float = 1.0, device=None, batch: int = 1):
         if dtype not in _DTYPES:
             raise TypeError(f"dtype must be torch.complex64 or torch.complex128, got {dtype}")
         self.lib = _lib.load()
         self.n = int(n)
+        self.batch = int(batch)
         self.dtype = dtype
         self.direction = int(direction)
         self.inplace = bool(inplace)
@@ -47,10 +50,10 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else torch.device(device).index or 0)
         with torch.cuda.device(self.device):
-            h = self.lib.efft_plan_scaled(self.n, _DTYPES[dtype], self.direction,
-                                          int(self.inplace), self.scale)
+            h = self.lib.efft_plan_many(self.n, self.batch, _DTYPES[dtype], self.direction,
+                                        int(self.inplace), self.scale)
         if not h:
-            raise EfftError(self.lib.efft_last_error(), "efft_plan")
+            raise EfftError(self.lib.efft_last_error(), "efft_plan_many")
         self.handle = ctypes.c_void_p(h)
         self.passes = self.lib.efft_plan_passes(self.handle)
         self.scratch_passes = self.lib.efft_plan_passes_scratch(self.handle)
@@ -60,7 +63,8 @@ class Plan:
         """A scratch tensor for ``execute(..., scratch=...)`` (None if unused)."""
         if self.scratch_bytes <= 0:
             return None
-        return torch.empty(self.n, dtype=self.dtype, device=self.device)
+        shape = (self.n,) if self.batch == 1 else (self.batch, self.n)
+        return torch.empty(shape, dtype=self.dtype, device=self.device)
 
     def _check(self, t: torch.Tensor, name: str):
         if t.dtype != self.dtype:
@@ -69,22 +73,26 @@ class Plan:
             raise ValueError(f"{name}: expected a tensor on {self.device}, got {t.device}")
         if t.shape[-1] != self.n:
             raise ValueError(f"{name}: last dimension {t.shape[-1]} != plan size {self.n}")
+        if (t.numel() // self.n if self.n else 0) % self.batch:
+            raise ValueError(f"{name}: {t.numel() // self.n} rows is not a multiple of the plan batch {self.batch}")
         if not t.is_contiguous():
             raise ValueError(f"{name}: tensor must be contiguous")
 
     def execute(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None,
                 scratch: torch.Tensor | None = None) -> torch.Tensor:
-        """Transform every length-N row of x; in place for in-place plans
-        (with ``scratch``, an N-element tensor of the plan's dtype, one pass
-        fewer)."""
+        """Transform every length-N row of x, ``batch`` rows per library call;
+        in place for in-place plans (with ``scratch``, a tensor of batch * N
+        elements of the plan's dtype, one pass fewer)."""
         self._check(x, "input")
         s = ctypes.c_void_p((stream or torch.cuda.current_stream(self.device)).cuda_stream)
-        rows = x.numel() // self.n if self.n else 0
+        rows = (x.numel() // self.n if self.n else 0) // self.batch
         xp = x.data_ptr()
-        step = self.n * x.element_size()
+        step = self.batch * self.n * x.element_size()
         if self.inplace:
             if scratch is not None:
                 self._check(scratch, "scratch")
+                if scratch.numel() < self.batch * self.n:
+                    raise ValueError("scratch: needs batch * N elements")
                 sp = ctypes.c_void_p(scratch.data_ptr())
                 for r in range(rows):
                     _lib.check(self.lib.efft_exec_scratch(self.handle, ctypes.c_void_p(xp + r * step), sp, s),
@@ -201,13 +209,13 @@ _cache_lock = threading.Lock()
 
 
 def get_plan(n: int, dtype: torch.dtype, direction: int, inplace: bool, scale: float,
-             device: torch.device) -> Plan:
-    """Cached plan keyed by (N, dtype, direction, in place, scale, device)."""
-    key = (int(n), dtype, int(direction), bool(inplace), float(scale), device)
+             device: torch.device, batch: int = 1) -> Plan:
+    """Cached plan keyed by (N, batch, dtype, direction, in place, scale, device)."""
+    key = (int(n), int(batch), dtype, int(direction), bool(inplace), float(scale), device)
     with _cache_lock:
         p = _cache.get(key)
         if p is None:
-            p = Plan(n, dtype, direction, inplace, scale, device)
+            p = Plan(n, dtype, direction, inplace, scale, device, batch)
             _cache[key] = p
         return p
 
@@ -226,7 +234,8 @@ def _transform(x: torch.Tensor, direction: int, scale: float, inplace: bool,
     if x.dtype not in _DTYPES:
         raise TypeError(f"dtype must be complex64 or complex128, got {x.dtype}")
     n = x.shape[-1]
-    p = get_plan(n, x.dtype, direction, inplace, scale, x.device)
+    rows = x.numel() // n if n else 1
+    p = get_plan(n, x.dtype, direction, inplace, scale, x.device, max(rows, 1))
     if inplace:
         return p.execute(x)
     return p.execute(x.contiguous(), out=out)

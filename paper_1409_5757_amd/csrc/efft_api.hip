@@ -149,6 +149,7 @@ enum PlanKind { KIND_C2C = 0, KIND_R2C = 1, KIND_C2R = 2 };
 struct efft_plan_s {
     uint64_t magic;
     int64_t n;
+    int64_t batch;  // contiguous signals of n points per execution
     int q, dtype, dir, inplace, eb;
     int m;
     int digits[MAX_DIGITS];
@@ -225,6 +226,17 @@ void build_passes(efft_plan_s *p, const TwTable &tt)
     }
     set_hints(p->passes);
     set_hints(p->scratch_passes);
+    // a batch of contiguous signals: every sub-FFT pass's lines simply
+    // continue into the next signal (blocks of the same structure), so only
+    // the tile count grows; the swap runs one grid layer per signal
+    for (std::vector<Pass> *v : {&p->passes, &p->scratch_passes}) {
+        for (Pass &ps : *v) {
+            if (ps.swap)
+                ps.wp.n = p->n;
+            else
+                ps.sp.ntiles *= p->batch;
+        }
+    }
 }
 
 // Scratch schedule of an in-place plan: the sub-FFT passes of digits
@@ -417,8 +429,8 @@ int run(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, voi
     return run_c2c(p->inner, out, out, stream, events ? events + 1 : nullptr, events ? nevents - 1 : 0);
 }
 
-int run_passes(const std::vector<Pass> &passes, int eb, const void *in, void *out, void *scratch,
-               hipStream_t stream, void **events, int nevents)
+int run_passes(const std::vector<Pass> &passes, int64_t batch, int eb, const void *in, void *out,
+               void *scratch, hipStream_t stream, void **events, int nevents)
 {
     if (events && nevents < int(passes.size()) + 1) return EFFT_ERR_ARG;
     for (size_t i = 0; i < passes.size(); ++i) {
@@ -429,7 +441,7 @@ int run_passes(const std::vector<Pass> &passes, int eb, const void *in, void *ou
         hipError_t e;
         if (ps.swap) {
             ps.wp.data = bufs[ps.dst];
-            e = launch_swap(eb, ps.wp, stream);
+            e = launch_swap(eb, ps.wp, batch, stream);
         } else {
             ps.sp.src = bufs[ps.src];
             ps.sp.dst = bufs[ps.dst];
@@ -445,7 +457,7 @@ int run_passes(const std::vector<Pass> &passes, int eb, const void *in, void *ou
 int run_c2c(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events,
             int nevents)
 {
-    return run_passes(p->passes, p->eb, in, out, nullptr, stream, events, nevents);
+    return run_passes(p->passes, p->batch, p->eb, in, out, nullptr, stream, events, nevents);
 }
 
 const efft_plan_s *live(const efft_plan_t *plan)
@@ -489,7 +501,7 @@ int make_tables(efft_plan_s *p, int q, TwTable *tt)
     return EFFT_OK;
 }
 
-efft_plan_s *create_c2c(int64_t n, int dtype, int dir, int inplace, double scale, int *status)
+efft_plan_s *create_c2c(int64_t n, int64_t batch, int dtype, int dir, int inplace, double scale, int *status)
 {
     efft_plan_s *p = new (std::nothrow) efft_plan_s();
     if (!p) {
@@ -498,6 +510,7 @@ efft_plan_s *create_c2c(int64_t n, int dtype, int dir, int inplace, double scale
     }
     p->magic = PLAN_MAGIC;
     p->n = n;
+    p->batch = batch;
     p->q = log2_exact(n);
     p->dtype = dtype;
     p->dir = dir;
@@ -542,13 +555,13 @@ int64_t in_bytes(const efft_plan_s *p)
 {
     if (p->kind == KIND_R2C) return p->n * p->eb / 2;
     if (p->kind == KIND_C2R) return (p->n / 2 + 1) * p->eb;
-    return p->n * p->eb;
+    return p->batch * p->n * p->eb;
 }
 int64_t out_bytes(const efft_plan_s *p)
 {
     if (p->kind == KIND_R2C) return (p->n / 2 + 1) * p->eb;
     if (p->kind == KIND_C2R) return p->n * p->eb / 2;
-    return p->n * p->eb;
+    return p->batch * p->n * p->eb;
 }
 
 int validate_scratch(const efft_plan_s *p, const void *data, const void *scratch)
@@ -556,7 +569,7 @@ int validate_scratch(const efft_plan_s *p, const void *data, const void *scratch
     int v = validate_ptr(p, scratch);
     if (v != EFFT_OK) return v;
     const uintptr_t a = reinterpret_cast<uintptr_t>(data), b = reinterpret_cast<uintptr_t>(scratch);
-    const uintptr_t bytes = uintptr_t(p->n) * uintptr_t(p->eb);
+    const uintptr_t bytes = uintptr_t(p->batch) * uintptr_t(p->n) * uintptr_t(p->eb);
     return (a < b + bytes && b < a + bytes) ? EFFT_ERR_OVERLAP : EFFT_OK;
 }
 
@@ -577,13 +590,20 @@ efft_plan_t *efft_plan(int64_t n, int dtype, int dir, int inplace)
 
 efft_plan_t *efft_plan_scaled(int64_t n, int dtype, int dir, int inplace, double scale)
 {
+    return efft_plan_many(n, 1, dtype, dir, inplace, scale);
+}
+
+efft_plan_t *efft_plan_many(int64_t n, int64_t batch, int dtype, int dir, int inplace, double scale)
+{
     const int q = log2_exact(n);
     int status = validate_args(q, dtype, dir, scale);
+    if (status == EFFT_OK && batch < 1) status = EFFT_ERR_ARG;
+    if (status == EFFT_OK && (batch > (int64_t(1) << 40) / n)) status = EFFT_ERR_SIZE;  // 2^40 points
     if (status != EFFT_OK) {
         g_last_error = status;
         return nullptr;
     }
-    efft_plan_s *p = create_c2c(n, dtype, dir, inplace, scale, &status);
+    efft_plan_s *p = create_c2c(n, batch, dtype, dir, inplace, scale, &status);
     if (!p) {
         g_last_error = status;
         return nullptr;
@@ -609,6 +629,7 @@ efft_plan_t *efft_plan_real(int64_t n, int dtype, int dir, double scale)
     }
     p->magic = PLAN_MAGIC;
     p->n = n;
+    p->batch = 1;
     p->q = q;
     p->dtype = dtype;
     p->dir = dir;
@@ -625,7 +646,7 @@ efft_plan_t *efft_plan_real(int64_t n, int dtype, int dir, double scale)
     // R2C: out-of-place forward N/2-point transform, scale applied by the
     // pairing pass; C2R: in-place backward N/2-point transform on the output,
     // scale applied by its last pass
-    p->inner = create_c2c(n / 2, dtype, dir, dir == EFFT_BACKWARD ? 1 : 0,
+    p->inner = create_c2c(n / 2, 1, dtype, dir, dir == EFFT_BACKWARD ? 1 : 0,
                           dir == EFFT_BACKWARD ? scale : 1.0, &status);
     if (!p->inner) {
         (void)hipFree(p->tables);
@@ -674,7 +695,7 @@ int efft_exec_events(const efft_plan_t *plan, const void *in, void *out, void *s
     if (scratch && !p->scratch_passes.empty()) {
         v = validate_scratch(p, out, scratch);
         if (v != EFFT_OK) return v;
-        return run_passes(p->scratch_passes, p->eb, in, out, scratch, static_cast<hipStream_t>(stream),
+        return run_passes(p->scratch_passes, p->batch, p->eb, in, out, scratch, static_cast<hipStream_t>(stream),
                           events, nevents);
     }
     return run(p, in, out, static_cast<hipStream_t>(stream), events, nevents);
@@ -690,7 +711,7 @@ int efft_exec_scratch(const efft_plan_t *plan, void *data, void *scratch, void *
     if (p->scratch_passes.empty()) return run(p, data, data, static_cast<hipStream_t>(stream), nullptr, 0);
     v = validate_scratch(p, data, scratch);
     if (v != EFFT_OK) return v;
-    return run_passes(p->scratch_passes, p->eb, data, data, scratch, static_cast<hipStream_t>(stream),
+    return run_passes(p->scratch_passes, p->batch, p->eb, data, data, scratch, static_cast<hipStream_t>(stream),
                       nullptr, 0);
 }
 
@@ -698,7 +719,7 @@ int64_t efft_scratch_bytes(const efft_plan_t *plan)
 {
     const efft_plan_s *p = live(plan);
     if (!p) return -1;
-    return p->scratch_passes.empty() ? 0 : p->n * p->eb;
+    return p->scratch_passes.empty() ? 0 : p->batch * p->n * p->eb;
 }
 
 int efft_plan_passes_scratch(const efft_plan_t *plan)
@@ -747,6 +768,12 @@ int64_t efft_plan_bytes(const efft_plan_t *plan)
     return p->table_bytes + (p->inner ? p->inner->table_bytes : 0);
 }
 
+int64_t efft_plan_batch(const efft_plan_t *plan)
+{
+    const efft_plan_s *p = live(plan);
+    return p ? p->batch : -1;
+}
+
 int efft_plan_passes(const efft_plan_t *plan)
 {
     const efft_plan_s *p = live(plan);
@@ -765,6 +792,7 @@ int efft_schedule(int64_t n, int dtype, int inplace, int *log2_radix, int max_di
     efft_plan_s probe{};
     probe.magic = PLAN_MAGIC;
     probe.n = n;
+    probe.batch = 1;
     probe.q = q;
     probe.dtype = dtype;
     probe.dir = EFFT_FORWARD;
@@ -782,7 +810,7 @@ int efft_schedule(int64_t n, int dtype, int inplace, int *log2_radix, int max_di
     std::vector<Pass> all = probe.passes;
     all.insert(all.end(), probe.scratch_passes.begin(), probe.scratch_passes.end());
     for (const Pass &ps : all) {
-        const hipError_t e = ps.swap ? launch_swap(eb, ps.wp, nullptr)
+        const hipError_t e = ps.swap ? launch_swap(eb, ps.wp, 1, nullptr)
                                      : launch_stage(eb, ps.layout, ps.logl, ps.lines, ps.sets, ps.sp, nullptr);
         if (e != hipSuccess) status = EFFT_ERR_SIZE;
     }

@@ -79,6 +79,7 @@ struct SwapParams {
     int64_t M;     // product of the middle digits (1 if none)
     int64_t nt;    // R / tile
     Digits mid;    // middle digits, lowest first
+    int64_t n;     // elements per signal (R * M * R)
     int nt_hint;   // 1: loads and stores carry the non-temporal (streaming) hint
 };
 
@@ -100,7 +101,8 @@ inline int64_t swap_tile(int dtype_bytes, int64_t R)
 // kernel launchers (efft_kernels.hip); return hipSuccess or the launch error
 hipError_t launch_stage(int dtype_bytes, int layout, int logl, int lines, int sets,
                         const StageParams &p, hipStream_t stream);
-hipError_t launch_swap(int dtype_bytes, const SwapParams &p, hipStream_t stream);
+// batch signals of p.n elements each, contiguous
+hipError_t launch_swap(int dtype_bytes, const SwapParams &p, int64_t batch, hipStream_t stream);
 hipError_t launch_twiddle_table(double2 *lo, int64_t n_lo, double2 *hi, int64_t n_hi, int h,
                                 int q, hipStream_t stream);
 hipError_t launch_r2c_post(int dtype_bytes, void *z, int64_t h, const TwTable &tt, double scale,

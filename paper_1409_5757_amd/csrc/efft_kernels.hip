@@ -218,6 +218,9 @@ __device__ __forceinline__ void finish_outputs(V *v, const StageParams &sp)
 // lines are far apart in memory over more DRAM channels.
 __device__ __forceinline__ int64_t order_tiles(int64_t bid, int64_t ntiles, int mode)
 {
+    // the multiplicative walk is a permutation only for a power-of-two count
+    // (a batch of 3 signals, say, has 3 * 2^k tiles): use the plain XCD order
+    if (mode == TILE_XCD_SCATTER && (ntiles & (ntiles - 1)) != 0) mode = TILE_XCD;
     if (mode == TILE_XCD && (ntiles & 7) == 0) return (bid & 7) * (ntiles >> 3) + (bid >> 3);
     if (mode == TILE_XCD_SCATTER && (ntiles & 63) == 0) {
         const int64_t c = ntiles >> 3, k = bid >> 3;  // c is a power of two
@@ -242,8 +245,10 @@ __device__ __forceinline__ TileLines<SETS> tile_lines(int64_t tile, int c, const
         const int64_t line = tile * (LINES * SETS) + st * LINES + c;
         if constexpr (LAYOUT == LAYOUT_ROW2COL) {
             // the tile's lines are LINES consecutive output columns; the source
-            // row of output column `line` is its digit reversal
-            a.blk[st] = int64_t(digit_reverse(uint64_t(line), sp.rev));
+            // row of output column `line` is its digit reversal within its
+            // signal (row_mul = N / L columns per signal of a batch)
+            const int64_t cols = sp.row_mul;
+            a.blk[st] = (line & ~(cols - 1)) | int64_t(digit_reverse(uint64_t(line & (cols - 1)), sp.rev));
             a.off[st] = 0;
             a.base[st] = a.blk[st] * L;
         } else {
@@ -312,13 +317,15 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
         __syncthreads();
         const int c2 = tid % LINES;
         const int t2 = tid / LINES;
-        const int64_t col = a.tile * LINES + c2;
+        const int64_t cols = sp.row_mul;
+        const int64_t line = a.tile * LINES + c2;
+        const int64_t col = (line & ~(cols - 1)) * L + (line & (cols - 1));  // signal * N + column
         const V *col_lds = lds + c2 * PADDED;
         V w[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) w[i] = col_lds[lds_pad(t2 + P * i)];
         finish_outputs<V, E>(w, sp);
-        store_points<V, E>(dst + col + sp.row_mul * int64_t(t2), sp.row_mul * int64_t(P), w, sp.nt_store);
+        store_points<V, E>(dst + col + cols * int64_t(t2), cols * int64_t(P), w, sp.nt_store);
     } else if constexpr (LAYOUT != LAYOUT_COL2ROW) {
 #pragma unroll
         for (int st = 0; st < SETS; ++st) {
@@ -339,14 +346,16 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
         __syncthreads();
         const int t2 = tid % P;
         const int c2 = tid / P;
-        const int64_t o2 = a.tile * LINES + c2;  // one block: line == offset
+        // one block per signal (B = N): line = signal * s + offset o2
+        const int64_t line = a.tile * LINES + c2;
+        const int64_t o2 = line & (sp.s - 1);
         const V *row_lds = lds + c2 * PADDED;
         V w[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) w[i] = row_lds[lds_pad(t2 + P * i)];
         apply_stage_twiddle<V, E, P>(w, t2, uint64_t(o2), sp.tw_scale, sp.tt);
         finish_outputs<V, E>(w, sp);
-        const int64_t row = sp.row_mul * int64_t(digit_reverse(uint64_t(o2), sp.rev));
+        const int64_t row = (line - o2) * L + sp.row_mul * int64_t(digit_reverse(uint64_t(o2), sp.rev));
         store_points<V, E>(dst + row + t2, int64_t(P), w, sp.nt_store);
     }
 }
@@ -448,7 +457,7 @@ __global__ void __launch_bounds__(NT) swap_kernel(SwapParams p)
     if (key > pkey) return;
     const bool self = (key == pkey);
 
-    V *x = static_cast<V *>(p.data);
+    V *x = static_cast<V *>(p.data) + int64_t(blockIdx.z) * p.n;  // signal of a batch
     const int col = threadIdx.x % TS;
     const int r0 = threadIdx.x / TS;
     // element (row a, col b) of tile A: x[((I*TS + a)*M + mu)*R + J*TS + b]
@@ -624,11 +633,10 @@ hipError_t launch_stage(int dtype_bytes, int layout, int logl, int lines, int se
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_swap(int dtype_bytes, const SwapParams &p, hipStream_t stream)
+static hipError_t launch_swap_z(int dtype_bytes, const SwapParams &p, unsigned nz, hipStream_t stream)
 {
     const int64_t ts = p.R / p.nt;
-    if (p.M > (int64_t(1) << 24) || p.nt * p.nt > 65535) return hipErrorInvalidValue;
-    const dim3 grid(unsigned(p.M), unsigned(p.nt * p.nt));
+    const dim3 grid(unsigned(p.M), unsigned(p.nt * p.nt), nz);
 #define EFFT_SWAP(T, TSV, NTV)                                                                      \
     if (ts == TSV) {                                                                                \
         if (g_dry_run) return hipSuccess;                                                           \
@@ -649,6 +657,19 @@ hipError_t launch_swap(int dtype_bytes, const SwapParams &p, hipStream_t stream)
     }
 #undef EFFT_SWAP
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_swap(int dtype_bytes, const SwapParams &p, int64_t batch, hipStream_t stream)
+{
+    if (p.M > (int64_t(1) << 24) || p.nt * p.nt > 65535) return hipErrorInvalidValue;
+    // signals of a batch along grid z, at most 65535 per launch
+    for (int64_t b0 = 0; b0 < batch; b0 += 65535) {
+        SwapParams q = p;
+        q.data = static_cast<char *>(p.data) + b0 * p.n * dtype_bytes;
+        const hipError_t e = launch_swap_z(dtype_bytes, q, unsigned(batch - b0 < 65535 ? batch - b0 : 65535), stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 void set_dry_run(bool on) { g_dry_run = on; }

@@ -49,6 +49,18 @@ def test_plan_scaled_rejects_bad_scale(lib):
         assert lib.efft_last_error() == -11
 
 
+def test_plan_many_rejects_bad_batch(lib):
+    """Batch checks run before any device work (CPU)."""
+    for b in (0, -1):
+        assert lib.efft_plan_many(1024, b, C64, -1, 1, 1.0) is None
+        assert lib.efft_last_error() == -11
+    assert lib.efft_plan_many(1 << 20, (1 << 20) + 1, C64, -1, 1, 1.0) is None  # > 2^40 points
+    assert lib.efft_last_error() == -1
+    assert lib.efft_plan_many(3 * 1024, 2, C64, -1, 1, 1.0) is None  # size check still applies
+    assert lib.efft_last_error() == -1
+    assert lib.efft_plan_batch(None) == -1
+
+
 def test_null_and_dead_handles(lib):
     assert lib.efft_destroy(None) == 0
     assert lib.efft_exec(None, None, None) == -4
