@@ -113,3 +113,10 @@ def bins_value(acc: np.ndarray) -> np.ndarray:
 def dft_at(x, bins, sign: int = -1, lib=None) -> np.ndarray:
     """One-shot direct DFT of the whole array ``x`` at ``bins``."""
     return bins_value(dft_bins(x, bins, sign=sign, lib=lib))
+
+
+def dft(x, sign: int = -1, lib=None) -> np.ndarray:
+    """Eq. "eqf" at every bin by the direct sum: O(N^2), any length N >= 1
+    (the reference for lengths that are not powers of two)."""
+    x = np.asarray(x)
+    return dft_at(x, np.arange(x.shape[0], dtype=np.int64), sign=sign, lib=lib)

@@ -26,12 +26,14 @@
  *                      directly (long double cosl/sinl of an exact ratio,
  *                      rounded once), never by recurrence.
  *
- *  oracle_dft_bins  -- Eq. "eqf" itself, evaluated at a few chosen bins k by
- *                      a direct sum over n, with the phase index (k*n) mod N
+ *  oracle_dft_bins  -- Eq. "eqf" itself, evaluated at chosen bins k by a
+ *                      direct sum over n, with the phase index (k*n) mod N
  *                      reduced exactly in integers and Kahan-compensated
- *                      accumulation.  Input may be streamed in chunks, so
- *                      sizes whose full array does not fit in host memory
- *                      can still be sampled.
+ *                      accumulation, for any length N (power of two or not;
+ *                      at all N bins it is the full O(N^2) definition).
+ *                      Input may be streamed in chunks, so sizes whose full
+ *                      array does not fit in host memory can still be
+ *                      sampled.
  *
  * Compile-time ORACLE_MUTANT=k (k > 0) plants one deliberate mistake; the
  * CPU test-suite builds those variants to show that its pins catch each one.
@@ -51,14 +53,18 @@
 
 static const long double PI_L = 3.14159265358979323846264338327950288L;
 
-/* exp(sign * 2*pi*i * num/den) rounded to double, den a power of two.
+/* exp(sign * 2*pi*i * num/den) rounded to double, for any den >= 1.
  * The turn num/den is split exactly into a whole number of quarter turns and
  * a remainder below a quarter turn, and a remainder above an eighth is taken
  * from the complementary angle, so cosl/sinl only ever see [0, pi/4] and
  * every multiple of a quarter turn (1, i, -1, -i) comes out exact. */
 static void unit_root(uint64_t num, uint64_t den, int sign, double *c, double *s)
 {
-    const uint64_t u = num & (den - 1u);           /* num mod den */
+#if ORACLE_MUTANT == 9 /* planted: the power-of-two shortcut for num mod den used for every den */
+    const uint64_t u = num & (den - 1u);
+#else
+    const uint64_t u = num % den;                  /* num mod den */
+#endif
     const uint64_t quads = (4u * u) / den;         /* whole quarter turns */
     const uint64_t rem = 4u * u - quads * den;     /* remainder, in den-ths of a quarter */
     long double cr, sr;
@@ -239,21 +245,26 @@ static inline void kahan_add(double *s, double *c, double v)
  *     sum_{j<len} x[j] * exp(sign*2*pi*i * ((k*(offset+j)) mod n) / n)
  * to acc[4*b .. 4*b+3] = (sum_re, comp_re, sum_im, comp_im) of bin bins[b]
  * (a Kahan pair per component), so a caller may stream the input in chunks
- * and call this once per chunk.  The phase index is reduced exactly in
- * 64-bit integers (n is a power of two, so the wrapped product keeps the
- * low bits exactly); the root of unity is the product of two directly
- * evaluated table entries exp(..hi*2^h/n) * exp(..lo/n).
- * Input is FP64 (is_f32 == 0, x is double*) or complex64 (is_f32 != 0, x is
- * float*, upcast exactly).  Returns 0, or -1 for a bad size.
+ * and call this once per chunk.  Any length n >= 1 is accepted.  The phase
+ * index m = (k*j) mod n is exact integer arithmetic: for a power-of-two n the
+ * wrapped 64-bit product keeps the low bits exactly; otherwise the product is
+ * formed in 128 bits at the first index of a run and advanced by k (mod n)
+ * from one index to the next.  The root of unity is the product of two
+ * directly evaluated table entries exp(..hi*2^h/n) * exp(..lo/n), m =
+ * hi*2^h + lo.  Input is FP64 (is_f32 == 0, x is double*) or complex64
+ * (is_f32 != 0, x is float*, upcast exactly).  Returns 0, or -1 for a bad
+ * size or slice.
  */
 int oracle_dft_bins(const void *x, int is_f32, int64_t offset, int64_t len, int64_t n,
                     int sign, const int64_t *bins, int64_t nb, double *acc)
 {
-    const int q = log2_exact(n);
-    if (q < 0 || offset < 0 || len < 0 || offset + len > n) return -1;
+    if (n <= 0 || offset < 0 || len < 0 || offset + len > n) return -1;
+    const int pow2 = (n & (n - 1)) == 0;
+    int q = 0; /* bits of n - 1 */
+    while (((int64_t)1 << q) < n) ++q;
     const int h = (q + 1) / 2;
     const int64_t n_lo = (int64_t)1 << h;
-    const int64_t n_hi = (int64_t)1 << (q - h);
+    const int64_t n_hi = (n + n_lo - 1) / n_lo; /* j with j * 2^h < n */
     const uint64_t mask = (uint64_t)n - 1u;
     double *t_lo = (double *)malloc(sizeof(double) * 2 * (size_t)n_lo);
     double *t_hi = (double *)malloc(sizeof(double) * 2 * (size_t)n_hi);
@@ -269,7 +280,7 @@ int oracle_dft_bins(const void *x, int is_f32, int64_t offset, int64_t len, int6
     const double *xd = (const double *)x;
     const float *xf = (const float *)x;
     for (int64_t b = 0; b < nb; ++b) {
-        const uint64_t k = (uint64_t)bins[b] & mask;
+        const uint64_t k = (uint64_t)(((bins[b] % n) + n) % n);
         int nth = oracle_threads();
         kahan_c *part = (kahan_c *)calloc((size_t)nth, sizeof(kahan_c));
 #pragma omp parallel num_threads(nth)
@@ -279,9 +290,23 @@ int oracle_dft_bins(const void *x, int is_f32, int64_t offset, int64_t len, int6
             tid = omp_get_thread_num();
 #endif
             kahan_c a = {0.0, 0.0, 0.0, 0.0};
+            int64_t prev = -2;
+            uint64_t m = 0;
 #pragma omp for schedule(static)
             for (int64_t j = 0; j < len; ++j) {
-                const uint64_t m = (k * (uint64_t)(offset + j)) & mask;
+                if (pow2) {
+                    m = (k * (uint64_t)(offset + j)) & mask;
+                } else if (j != prev + 1) {
+#if ORACLE_MUTANT == 10 /* planted: the product wraps at 2^64 before the reduction mod n */
+                    m = (k * (uint64_t)(offset + j)) % (uint64_t)n;
+#else
+                    m = (uint64_t)(((unsigned __int128)k * (unsigned __int128)(uint64_t)(offset + j)) % (uint64_t)n);
+#endif
+                } else {
+                    m += k; /* (k*(j+1)) mod n from (k*j) mod n */
+                    if (m >= (uint64_t)n) m -= (uint64_t)n;
+                }
+                prev = j;
                 const uint64_t mh = m >> h, ml = m & (uint64_t)(n_lo - 1);
                 const double hr = t_hi[2 * mh], hi = t_hi[2 * mh + 1];
                 const double lr = t_lo[2 * ml], li = t_lo[2 * ml + 1];

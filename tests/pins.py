@@ -161,4 +161,45 @@ def battery(lib) -> list[str]:
     check("roundtrip", rel_l2(fft(fx, +1) / n, x) < 1e-15)
     # 14. backward is the conjugate-sign transform: bwd(x) = conj(fwd(conj(x)))
     check("backward_conj", rel_l2(fft(x, +1), np.conj(fft(np.conj(x)))) < 1e-15)
+
+    # Lengths that are not powers of two (the direct-sum route, oracle.dft)
+    def dft(x, sign=-1):
+        return oracle.dft(x, sign, lib=lib)
+
+    # 15. brute-force definition, both signs
+    for n in (3, 5, 6, 7, 12, 30, 100, 243, 1000):
+        r = _rng(1000 + n)
+        x = r.uniform(-1, 1, n) + 1j * r.uniform(-1, 1, n)
+        for sign in (-1, 1):
+            check(f"brute_any:n={n}:s={sign}", rel_l2(dft(x, sign), brute_dft(x, sign)) < 1e-14)
+    # 16. arbitrary precision at N = 15
+    r = _rng(15)
+    x = r.uniform(-0.5, 0.5, 15) + 1j * r.uniform(-0.5, 0.5, 15)
+    ref = np.array([complex(v) for v in mp_dft(x)], dtype=np.complex128)
+    check("mpmath_any:n=15", rel_l2(dft(x), ref) < 1e-15)
+    # 17. numpy's FFT (pocketfft, mixed radix and Bluestein) at a prime and a
+    #     composite length
+    for n in (9973, 3 * 5 * 7 * 11 * 4):
+        r = _rng(n)
+        x = r.standard_normal(n) + 1j * r.standard_normal(n)
+        check(f"numpy_any:n={n}", rel_l2(dft(x), np.fft.fft(x)) < 1e-13)
+    # 18. closed forms at N = 1500: impulse, and the geometric series
+    n = 1500
+    k = np.arange(n)
+    imp = np.zeros(n, dtype=np.complex128)
+    imp[7] = 1
+    check("impulse_any", np.max(np.abs(dft(imp) - np.exp(-2j * np.pi * ((k * 7) % n) / n))) < 1e-14)
+    g = rr ** np.arange(n)
+    closed = (1 - rr ** n) / (1 - rr * np.exp(-2j * np.pi * k / n))
+    check("geometric_any", rel_l2(dft(g), closed) < 1e-13)
+    # 19. exact phase reduction far beyond 2^64 at a length that is not a power
+    #     of two: a tone at frequency f sampled over a slice near the end sums
+    #     to the slice length in the tone's bin
+    n = 3 * (1 << 32) + 7
+    f = (1 << 32) + 12345
+    off = n - 3000
+    ph = np.array([((f * j) % n) / n for j in range(off, off + 3000)])  # exact integers, then one division
+    tone = np.exp(2j * np.pi * ph)
+    val = oracle.bins_value(oracle.dft_bins(tone, [f], n=n, offset=off, lib=lib))[0]
+    check("spot_any_phase", abs(val - 3000) < 1e-8)
     return failed

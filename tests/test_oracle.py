@@ -16,7 +16,7 @@ def test_battery_passes_on_oracle(oracle_lib):
     assert pins.battery(oracle_lib) == []
 
 
-@pytest.mark.parametrize("mutant", range(1, 9))
+@pytest.mark.parametrize("mutant", range(1, 11))
 def test_battery_catches_planted_mistake(mutant):
     """Each planted mistake (sign, reordering, twiddle index, dropped twiddle,
     swapped outputs, wrong operand, skipped k=0, short bit reversal) must
@@ -129,3 +129,12 @@ def test_random_sizes_against_definition(oracle_lib, q, seed, sign):
     rng = np.random.default_rng(seed)
     x = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
     assert pins.rel_l2(oracle.fft(x, sign), pins.brute_dft(x, sign)) < 1e-14
+
+
+@settings(max_examples=25, deadline=None)
+@given(n=st.integers(min_value=1, max_value=400), seed=st.integers(0, 2**31 - 1),
+       sign=st.sampled_from([-1, 1]))
+def test_direct_dft_any_length_against_definition(oracle_lib, n, seed, sign):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
+    assert pins.rel_l2(oracle.dft(x, sign), pins.brute_dft(x, sign)) < 1e-14
