@@ -63,7 +63,7 @@ enum { EFFT_FORWARD = -1, EFFT_BACKWARD = 1 };
 /* status codes */
 enum {
     EFFT_OK = 0,
-    EFFT_ERR_SIZE = -1,      /* n is not 2^q with 0 <= q <= EFFT_MAX_LOG2N */
+    EFFT_ERR_SIZE = -1,      /* n is neither 2^q (0 <= q <= EFFT_MAX_LOG2N) nor 3 <= n <= 2^(EFFT_MAX_LOG2N-1) */
     EFFT_ERR_DTYPE = -2,     /* dtype is neither EFFT_C64 nor EFFT_C128 */
     EFFT_ERR_DIR = -3,       /* dir is neither EFFT_FORWARD nor EFFT_BACKWARD */
     EFFT_ERR_NULLPTR = -4,   /* a required pointer is NULL */
@@ -81,12 +81,25 @@ enum {
 #define EFFT_MAX_LOG2N 34
 
 /*
- * Create a plan for an N-point transform.  n = N = 2^q (0 <= q <= 34);
+ * Create a plan for an N-point transform.  n = N = 2^q (0 <= q <= 34), or any
+ * other length 3 <= N <= 2^33;
  * dtype = EFFT_C64 or EFFT_C128; dir = EFFT_FORWARD or EFFT_BACKWARD;
  * inplace != 0 makes an in-place plan (executed with efft_exec), inplace == 0
  * an out-of-place plan (executed with efft_exec_oop).  Builds the FP64 twiddle
  * tables on the current device and waits for that to finish.  Returns NULL on
  * failure, with the reason in efft_last_error().
+ *
+ * A length that is not a power of two (the paper's EFFT takes N = M * 2^s,
+ * Section 2.2 and Section 4, with MKL doing the M-point bin DFTs) is
+ * transformed through the chirp identity n*k = (n^2 + k^2 - (k-n)^2)/2:
+ * F_k = a_k sum_n (x_n a_n) conj(a_{k-n}), a_m = exp(sign*pi*i*m^2/N), a
+ * linear convolution done as a cyclic one of length M = 2^ceil(log2(2N-1))
+ * with the library's power-of-two passes.  Such a plan owns, on the device,
+ * the chirp (N FP64 complex values), the transformed convolution kernel and
+ * a work array (M elements of dtype each; see efft_plan_bytes), so at most
+ * one execution of it may be in flight at a time.  Each execution runs, per
+ * signal: a pre-multiply pass, an M-point forward transform, a pointwise
+ * product, an M-point backward transform and a post-multiply pass.
  */
 efft_plan_t *efft_plan(int64_t n, int dtype, int dir, int inplace);
 
@@ -191,7 +204,9 @@ int efft_last_error(void);
 /* Static, human-readable name of a status code. */
 const char *efft_strerror(int status);
 
-/* Device bytes held by the plan (its twiddle tables); -1 for a bad handle. */
+/* Device bytes held by the plan (its twiddle tables, and for a length that is
+ * not a power of two also the chirp, kernel and work arrays); -1 for a bad
+ * handle. */
 int64_t efft_plan_bytes(const efft_plan_t *plan);
 
 /* Number of kernel launches one execution enqueues; -1 for a bad handle. */

@@ -8,8 +8,9 @@
 ``rfft(x)``  real input of length N -> bins F_0 .. F_{N/2} (N/2 + 1 complex).
 ``irfft(X)`` N/2 + 1 Hermitian bins -> N real samples, scaled by 1/N.
 
-Inputs are complex64 / complex128 CUDA tensors whose last dimension is a
-power of two (N = 2^q, q <= 34).  Leading dimensions are a batch of
+Inputs are complex64 / complex128 CUDA tensors whose last dimension N is a
+power of two (N = 2^q, q <= 34) or any other length 3 <= N <= 2^33 (done by
+the library's chirp path; ``ifft`` then scales by the rounded 1/N).  Leading dimensions are a batch of
 independent transforms, done by one batched plan (every pass of the
 transform covers all rows at once).  All work runs in ``libefft.so`` on the
 tensor's device, on the current torch stream; there is no CPU fallback.

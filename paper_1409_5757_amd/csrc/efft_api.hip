@@ -144,7 +144,7 @@ int dtype_bytes(int dtype) { return dtype == EFFT_C128 ? 16 : dtype == EFFT_C64 
 
 }  // namespace
 
-enum PlanKind { KIND_C2C = 0, KIND_R2C = 1, KIND_C2R = 2 };
+enum PlanKind { KIND_C2C = 0, KIND_R2C = 1, KIND_C2R = 2, KIND_CHIRP = 3 };
 
 struct efft_plan_s {
     uint64_t magic;
@@ -165,6 +165,13 @@ struct efft_plan_s {
     int kind;
     efft_plan_s *inner;
     TwTable tt_real;
+    // lengths that are not powers of two (KIND_CHIRP): the chirp a_j (FP64),
+    // the transformed kernel V = DFT_M(v)/M and a work array of M points, with
+    // forward (inner) and backward (inner2) in-place M-point plans
+    int64_t m_pad;
+    efft_plan_s *inner2;
+    double2 *chirp;
+    void *vhat, *work;
 };
 
 namespace {
@@ -401,13 +408,45 @@ int run_c2c(const efft_plan_s *p, const void *in, void *out, hipStream_t stream,
 
 int total_passes(const efft_plan_s *p)
 {
-    return p->kind == KIND_C2C ? int(p->passes.size()) : int(p->inner->passes.size()) + 1;
+    if (p->kind == KIND_C2C) return int(p->passes.size());
+    if (p->kind == KIND_CHIRP)  // premul, M-point forward, product, M-point backward, postmul
+        return int(p->inner->passes.size()) + int(p->inner2->passes.size()) + 3;
+    return int(p->inner->passes.size()) + 1;
+}
+
+// Chirp plan: per signal, w = (x a) zero-padded; w = DFT_M(w); w *= V;
+// w = DFT_M^-(w) (the 1/M is in V); out = scale * a * w[0 .. N).
+int run_chirp(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events, int nevents)
+{
+    const int np = total_passes(p);
+    if (events && (nevents < np + 1 || p->batch != 1)) return EFFT_ERR_ARG;
+    auto rec = [&](int i) {
+        return !events || hipEventRecord(static_cast<hipEvent_t>(events[i]), stream) == hipSuccess;
+    };
+    const int nf = int(p->inner->passes.size()), nb = int(p->inner2->passes.size());
+    for (int64_t b = 0; b < p->batch; ++b) {
+        const char *x = static_cast<const char *>(in) + b * p->n * p->eb;
+        char *y = static_cast<char *>(out) + b * p->n * p->eb;
+        if (!rec(0) || launch_premul(p->eb, x, p->work, p->chirp, p->n, p->m_pad, stream) != hipSuccess)
+            return EFFT_ERR_HIP;
+        int r = run_c2c(p->inner, p->work, p->work, stream, events ? events + 1 : nullptr, events ? nf + 1 : 0);
+        if (r != EFFT_OK) return r;
+        if (!rec(nf + 1) || launch_pointwise(p->eb, p->work, p->vhat, p->m_pad, stream) != hipSuccess)
+            return EFFT_ERR_HIP;
+        r = run_c2c(p->inner2, p->work, p->work, stream, events ? events + nf + 2 : nullptr, events ? nb + 1 : 0);
+        if (r != EFFT_OK) return r;
+        if (!rec(nf + nb + 2) || launch_postmul(p->eb, p->work, y, p->chirp, p->n, p->scale, stream) != hipSuccess)
+            return EFFT_ERR_HIP;
+        if (!rec(np)) return EFFT_ERR_HIP;
+    }
+    return EFFT_OK;
 }
 
 int run(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events,
         int nevents)
 {
     if (p->kind == KIND_C2C) return run_c2c(p, in, out, stream, events, nevents);
+    if (p->kind == KIND_CHIRP) return run_chirp(p, in, out, stream, events, nevents);
     const int np = total_passes(p);
     if (events && nevents < np + 1) return EFFT_ERR_ARG;
     const int64_t h = p->n / 2;
@@ -465,6 +504,10 @@ const efft_plan_s *live(const efft_plan_t *plan)
     if (!plan || !registered(plan)) return nullptr;
     return plan->magic == PLAN_MAGIC ? plan : nullptr;
 }
+
+// largest length that is not a power of two: its padded length 2^ceil(log2(2n-1))
+// is at most 2^EFFT_MAX_LOG2N
+constexpr int64_t MAX_CHIRP_N = (int64_t(1) << (EFFT_MAX_LOG2N - 1));
 
 int validate_args(int q, int dtype, int dir, double scale)
 {
@@ -540,8 +583,61 @@ void free_plan(efft_plan_s *p)
     if (!p) return;
     p->magic = 0;
     if (p->tables) (void)hipFree(p->tables);
+    if (p->chirp) (void)hipFree(p->chirp);
+    if (p->vhat) (void)hipFree(p->vhat);
+    if (p->work) (void)hipFree(p->work);
     free_plan(p->inner);
+    free_plan(p->inner2);
     delete p;
+}
+
+// Plan for a length n >= 3 that is not a power of two: two in-place plans of
+// M = 2^ceil(log2(2n - 1)) points, the chirp and the transformed kernel are
+// built here (on the current device), once.
+efft_plan_s *create_chirp(int64_t n, int64_t batch, int dtype, int dir, int inplace, double scale, int *status)
+{
+    int64_t m = 1;
+    while (m < 2 * n - 1) m *= 2;
+    efft_plan_s *p = new (std::nothrow) efft_plan_s();
+    if (!p) {
+        *status = EFFT_ERR_ALLOC;
+        return nullptr;
+    }
+    p->magic = PLAN_MAGIC;
+    p->n = n;
+    p->batch = batch;
+    p->q = -1;
+    p->dtype = dtype;
+    p->dir = dir;
+    p->inplace = inplace ? 1 : 0;
+    p->eb = dtype_bytes(dtype);
+    p->scale = scale;
+    p->kind = KIND_CHIRP;
+    p->m_pad = m;
+    p->inner = create_c2c(m, 1, dtype, EFFT_FORWARD, 1, 1.0, status);
+    if (p->inner) p->inner2 = create_c2c(m, 1, dtype, EFFT_BACKWARD, 1, 1.0, status);
+    if (!p->inner || !p->inner2) {
+        free_plan(p);
+        return nullptr;
+    }
+    const size_t eb = size_t(p->eb);
+    if (hipMalloc(reinterpret_cast<void **>(&p->chirp), size_t(n) * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->vhat, size_t(m) * eb) != hipSuccess || hipMalloc(&p->work, size_t(m) * eb) != hipSuccess) {
+        (void)hipGetLastError();
+        free_plan(p);
+        *status = EFFT_ERR_ALLOC;
+        return nullptr;
+    }
+    p->table_bytes = int64_t(n) * int64_t(sizeof(double2)) + 2 * m * int64_t(eb);
+    if (launch_chirp(p->chirp, n, dir, nullptr) != hipSuccess ||
+        launch_chirp_v(p->eb, p->vhat, p->chirp, n, m, nullptr) != hipSuccess ||
+        run_c2c(p->inner, p->vhat, p->vhat, nullptr, nullptr, 0) != EFFT_OK || hipDeviceSynchronize() != hipSuccess) {
+        free_plan(p);
+        *status = EFFT_ERR_HIP;
+        return nullptr;
+    }
+    *status = EFFT_OK;
+    return p;
 }
 
 void register_plan(efft_plan_s *p)
@@ -595,7 +691,8 @@ efft_plan_t *efft_plan_scaled(int64_t n, int dtype, int dir, int inplace, double
 
 efft_plan_t *efft_plan_many(int64_t n, int64_t batch, int dtype, int dir, int inplace, double scale)
 {
-    const int q = log2_exact(n);
+    const bool chirp = n >= 3 && n <= MAX_CHIRP_N && log2_exact(n) < 0;
+    const int q = chirp ? 1 : log2_exact(n);  // the remaining checks are size-independent
     int status = validate_args(q, dtype, dir, scale);
     if (status == EFFT_OK && batch < 1) status = EFFT_ERR_ARG;
     if (status == EFFT_OK && (batch > (int64_t(1) << 40) / n)) status = EFFT_ERR_SIZE;  // 2^40 points
@@ -603,7 +700,8 @@ efft_plan_t *efft_plan_many(int64_t n, int64_t batch, int dtype, int dir, int in
         g_last_error = status;
         return nullptr;
     }
-    efft_plan_s *p = create_c2c(n, batch, dtype, dir, inplace, scale, &status);
+    efft_plan_s *p = chirp ? create_chirp(n, batch, dtype, dir, inplace, scale, &status)
+                           : create_c2c(n, batch, dtype, dir, inplace, scale, &status);
     if (!p) {
         g_last_error = status;
         return nullptr;
@@ -746,7 +844,7 @@ const char *efft_strerror(int status)
 {
     switch (status) {
     case EFFT_OK: return "EFFT_OK: success";
-    case EFFT_ERR_SIZE: return "EFFT_ERR_SIZE: n must be 2^q with 0 <= q <= 34";
+    case EFFT_ERR_SIZE: return "EFFT_ERR_SIZE: n must be 2^q (0 <= q <= 34) or another length 3 <= n <= 2^33";
     case EFFT_ERR_DTYPE: return "EFFT_ERR_DTYPE: dtype must be EFFT_C64 or EFFT_C128";
     case EFFT_ERR_DIR: return "EFFT_ERR_DIR: dir must be EFFT_FORWARD (-1) or EFFT_BACKWARD (+1)";
     case EFFT_ERR_NULLPTR: return "EFFT_ERR_NULLPTR: required pointer is NULL";
@@ -765,7 +863,7 @@ int64_t efft_plan_bytes(const efft_plan_t *plan)
 {
     const efft_plan_s *p = live(plan);
     if (!p) return -1;
-    return p->table_bytes + (p->inner ? p->inner->table_bytes : 0);
+    return p->table_bytes + (p->inner ? p->inner->table_bytes : 0) + (p->inner2 ? p->inner2->table_bytes : 0);
 }
 
 int64_t efft_plan_batch(const efft_plan_t *plan)

@@ -109,6 +109,19 @@ hipError_t launch_r2c_post(int dtype_bytes, void *z, int64_t h, const TwTable &t
                            int apply_scale, hipStream_t stream);
 hipError_t launch_c2r_pre(int dtype_bytes, const void *f, void *z, int64_t h, const TwTable &tt,
                           hipStream_t stream);
+// lengths that are not powers of two (chirp form, efft_bluestein.hip):
+// a[j] = exp(sign*pi*i * (j^2 mod 2N)/N) for j < n (FP64)
+hipError_t launch_chirp(double2 *a, int64_t n, int sign, hipStream_t stream);
+// w[0..m) = conj(a_j)/m at j and m - j (0 <= j < n), zero elsewhere
+hipError_t launch_chirp_v(int dtype_bytes, void *w, const double2 *a, int64_t n, int64_t m, hipStream_t stream);
+// w[0..m) = (x a) zero-padded
+hipError_t launch_premul(int dtype_bytes, const void *x, void *w, const double2 *a, int64_t n, int64_t m,
+                         hipStream_t stream);
+// w *= v over m points
+hipError_t launch_pointwise(int dtype_bytes, void *w, const void *v, int64_t m, hipStream_t stream);
+// out[0..n) = scale * a * w
+hipError_t launch_postmul(int dtype_bytes, const void *w, void *out, const double2 *a, int64_t n, double scale,
+                          hipStream_t stream);
 // while on (per host thread), launch_stage / launch_swap only check that a
 // kernel exists for the arguments and launch nothing
 void set_dry_run(bool on);

@@ -33,9 +33,10 @@ def test_status_names(lib):
 
 
 @pytest.mark.parametrize("n,dtype,direction,inplace,status", [
-    (12, C64, -1, 1, -1), (0, C64, -1, 1, -1), (-8, C128, -1, 0, -1), (1 << 35, C64, -1, 1, -1),
-    (3, C128, 1, 0, -1), (1024, 0, -1, 1, -2), (1024, 3, -1, 1, -2), (1024, C64, 0, 1, -3),
-    (1024, C64, 2, 0, -3),
+    (0, C64, -1, 1, -1), (-8, C128, -1, 0, -1), (1 << 35, C64, -1, 1, -1),
+    ((1 << 33) + 3, C128, 1, 0, -1), ((1 << 34) - 1, C64, -1, 1, -1),
+    (1024, 0, -1, 1, -2), (1024, 3, -1, 1, -2), (1024, C64, 0, 1, -3), (1024, C64, 2, 0, -3),
+    (12, 0, -1, 1, -2), (1000, C64, 0, 1, -3),
 ])
 def test_plan_rejects_invalid_arguments(lib, n, dtype, direction, inplace, status):
     """Invalid arguments are rejected before any device work (runs on CPU)."""
@@ -56,7 +57,7 @@ def test_plan_many_rejects_bad_batch(lib):
         assert lib.efft_last_error() == -11
     assert lib.efft_plan_many(1 << 20, (1 << 20) + 1, C64, -1, 1, 1.0) is None  # > 2^40 points
     assert lib.efft_last_error() == -1
-    assert lib.efft_plan_many(3 * 1024, 2, C64, -1, 1, 1.0) is None  # size check still applies
+    assert lib.efft_plan_many((1 << 33) + 1, 2, C64, -1, 1, 1.0) is None  # size check still applies
     assert lib.efft_last_error() == -1
     assert lib.efft_plan_batch(None) == -1
 

@@ -1,0 +1,86 @@
+"""Lengths that are not powers of two (the chirp path): every bin against the
+oracle's direct sum of Eq. "eqf" up to N ~ 10^4, sampled bins against it at
+larger N, closed-form tones, round trips, batches, and argument handling.
+Tolerances are the path's bars (FP64 rel-L2 <= 1e-12, FP32 <= 1e-5); for
+sampled bins the error of each bin is taken relative to the RMS of the
+spectrum, which equals ||x||_2 (Parseval)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1409_5757_amd import api
+from tests.gpu_util import NP, TOL, host_input, oracle_bins_from_device, rel_l2, run_library, sample_bins
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.complex128, torch.complex64]
+FULL_SIZES = [3, 5, 6, 7, 9, 12, 15, 100, 243, 1000, 1536, 4097, 9973]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_every_bin_against_direct_sum(dtype):
+    for i, n in enumerate(FULL_SIZES):
+        x = host_input("uniform", 3000 + n, n, dtype)
+        direction = -1 if i % 2 == 0 else 1
+        inplace = i % 3 == 0
+        got, after = run_library(x, dtype, direction, inplace)
+        ref = oracle.dft(x, direction)
+        err = rel_l2(got, ref)
+        print(f"n={n} {dtype} dir={direction} inplace={inplace}: rel_l2={err:.2e}", flush=True)
+        assert err <= TOL[dtype], (n, err)
+        if after is not None:
+            np.testing.assert_array_equal(after, x)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [3 * (1 << 20), 5 ** 10, 10 ** 7 + 1])
+def test_sampled_bins_large(dtype, n):
+    x = torch.from_numpy(host_input("normal", 17, n, dtype)).cuda()
+    y = api.fft(x)
+    bins = sample_bins(n, 24, seed=n % 1000)
+    ref = oracle_bins_from_device(x, bins)
+    scale = float(torch.linalg.vector_norm(x.to(torch.complex128)))
+    err = float(np.max(np.abs(y[torch.from_numpy(bins).cuda()].cpu().numpy() - ref))) / scale
+    print(f"n={n} {dtype}: max bin error / rms = {err:.2e}", flush=True)
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_tone_closed_form(dtype):
+    """x_j = exp(2 pi i (f j mod N)/N + i phi) -> N e^{i phi} at f, 0 elsewhere."""
+    n = 1_000_003  # prime
+    f, phi = 123_457, 0.7
+    j = np.arange(n, dtype=np.int64)
+    x = np.exp(2j * np.pi * ((f * j) % n) / n + 1j * phi).astype(NP[dtype])
+    got, _ = run_library(x, dtype, -1, False)
+    tol = 1e-9 * n if dtype == torch.complex128 else 2e-4 * n
+    assert abs(got[f] - n * np.exp(1j * phi)) < tol
+    rest = got.copy()
+    rest[f] = 0
+    assert np.max(np.abs(rest)) < tol
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_round_trip_and_batch(dtype):
+    for n in (1000, 3 * (1 << 16) + 1):
+        x = torch.from_numpy(np.stack([host_input("uniform", 50 + r, n, dtype) for r in range(3)])).cuda()
+        y = api.fft(x)               # one batched plan of 3 signals
+        z = api.ifft(y)
+        assert rel_l2(z.cpu().numpy(), x.cpu().numpy()) < (1e-13 if dtype == torch.complex128 else 3e-6)
+        # each row of the batch equals the same signal transformed alone (bit for bit)
+        for r in range(3):
+            alone = api.fft(x[r].contiguous())
+            assert torch.equal(alone, y[r])
+        # and the in-place plan gives the same bits as the out-of-place one
+        w = x.clone()
+        api.fft(w, inplace=True)
+        assert torch.equal(w, y)
+        torch.cuda.synchronize()
+
+
+def test_plan_reports_memory_and_passes():
+    p = api.Plan(1000, torch.complex128, -1, False, device=torch.device("cuda", 0))
+    # chirp (FP64) + V + work of M = 2048 points, plus the two inner plans' tables
+    assert p.device_bytes() >= 1000 * 16 + 2 * 2048 * 16
+    assert p.passes >= 5 and p.scratch_bytes == 0
