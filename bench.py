@@ -129,6 +129,7 @@ def main() -> int:
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-real", action="store_true")
+    ap.add_argument("--no-anylen", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one transform on one GPU; runs on more than one GPU are not "
@@ -237,6 +238,24 @@ def main() -> int:
                                "passes": pr.passes}
         del xr, yr
         pr.close()
+        torch.cuda.empty_cache()
+
+    if not args.no_anylen:
+        # a length that is not a power of two (the paper's N = M * 2^s class):
+        # the chirp path, two M = 2^(q+1)-point transforms plus three
+        # elementwise passes; GFLOP/s by the same nominal 5 N log2 N
+        na = 3 << (q - 2)
+        xa = torch.empty(na, dtype=torch.complex128, device=dev)
+        inputs.fill_uniform_torch(xa, seed=0)
+        pa = api.Plan(na, torch.complex128, -1, True, device=dev)
+        msa, eva, ppa = time_transform(pa, xa, max(2, args.steps // 2), 1)
+        result["any_length"] = {
+            "workload": f"forward in-place N=3*2^{q - 2} complex128 (chirp path, M=2^{q + 1})",
+            "value": round(5 * na * math.log2(na) / (msa * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+            "ms_per_step": round(msa, 4), "passes": pa.passes,
+            "ms_per_pass": [round(t, 4) for t in ppa]}
+        del xa
+        pa.close()
         torch.cuda.empty_cache()
 
     result["copy_ceiling_GBps"] = round(copy_ceiling(min(8 << 30, n * 16)), 1)

@@ -128,6 +128,43 @@ efft_plan_t *efft_plan_many(int64_t n, int64_t batch, int dtype, int dir, int in
 int64_t efft_plan_batch(const efft_plan_t *plan);
 
 /*
+ * As efft_plan_many for N = 2^q, with the decomposition N = 2^d_0 * ... *
+ * 2^d_{m-1} chosen by the caller (log2_digits[i] = d_i, slowest input digit
+ * first) instead of by the planner -- the GPU form of the paper's tuning
+ * scan over the number of splits (Section 5.2, Fig. "fig:heatmap"; see
+ * efft_set_pass_options for the other knobs).  The digits must sum to q;
+ * with m = 1, q <= 12; with m > 1 every digit lies in [4, 10] and an in-place
+ * plan needs a palindrome (d_i = d_{m-1-i}).  Returns NULL with EFFT_ERR_ARG
+ * for an unusable decomposition, EFFT_ERR_NULLPTR if log2_digits is NULL, and
+ * the codes of efft_plan_many otherwise.
+ */
+efft_plan_t *efft_plan_digits(int64_t n, int64_t batch, int dtype, int dir, int inplace, double scale,
+                              const int *log2_digits, int m);
+
+/*
+ * Launch options of pass `pass` (0-based) of a power-of-two plan's schedule:
+ * scratch = 0 selects the plain schedule (efft_exec / efft_exec_oop),
+ * scratch = 1 the scratch schedule (efft_exec_scratch).  opts[0..5]:
+ *   opts[0] layout (read only: 0 contiguous lines, 1 strided lines,
+ *           2 strided lines written as rows, 3 rows written as strided
+ *           lines, -1 the digit-reversal swap),
+ *   opts[1] lines per line set of a workgroup, opts[2] line sets per
+ *           workgroup, opts[3] tile order (0 linear, 1 one contiguous run
+ *           per XCD, 2 the same walked with an odd stride),
+ *   opts[4] non-temporal loads, opts[5] non-temporal stores (0/1; for the
+ *           swap opts[4] sets both).
+ * efft_pass_options reads them; efft_set_pass_options replaces them if a
+ * kernel exists for the combination (else EFFT_ERR_ARG, plan unchanged).
+ * They decide which workgroup transforms which lines and how memory is
+ * accessed, never the arithmetic: every valid setting gives bit-identical
+ * results.  Setting options must not overlap an execution of the plan.
+ * EFFT_ERR_PLAN_KIND for real-input plans and lengths that are not powers of
+ * two.
+ */
+int efft_pass_options(const efft_plan_t *plan, int scratch, int pass, int *opts);
+int efft_set_pass_options(efft_plan_t *plan, int scratch, int pass, const int *opts);
+
+/*
  * Real-data plan for N = 2^q real samples (1 <= q <= 34), always out of
  * place, executed with efft_exec_oop.  The paper's EFFT transforms real data
  * (Section 2.1 "code:dfti", Section 4); this keeps the standard half-spectrum

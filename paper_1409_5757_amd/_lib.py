@@ -43,6 +43,12 @@ def _bind(lib):
     lib.efft_plan_many.restype = vp
     lib.efft_plan_batch.argtypes = [vp]
     lib.efft_plan_batch.restype = i64
+    lib.efft_plan_digits.argtypes = [i64, i64, ci, ci, ci, ctypes.c_double, ctypes.POINTER(ci), ci]
+    lib.efft_plan_digits.restype = vp
+    lib.efft_pass_options.argtypes = [vp, ci, ci, ctypes.POINTER(ci)]
+    lib.efft_pass_options.restype = ci
+    lib.efft_set_pass_options.argtypes = [vp, ci, ci, ctypes.POINTER(ci)]
+    lib.efft_set_pass_options.restype = ci
     lib.efft_plan_real.argtypes = [i64, ci, ci, ctypes.c_double]
     lib.efft_plan_real.restype = vp
     lib.efft_exec.argtypes = [vp, vp, vp]

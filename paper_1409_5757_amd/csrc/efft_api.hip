@@ -544,7 +544,42 @@ int make_tables(efft_plan_s *p, int q, TwTable *tt)
     return EFFT_OK;
 }
 
-efft_plan_s *create_c2c(int64_t n, int64_t batch, int dtype, int dir, int inplace, double scale, int *status)
+// every pass of the plan's schedules has a kernel (host-side dry run)
+bool kernels_exist(const efft_plan_s *p)
+{
+    set_dry_run(true);
+    bool ok = true;
+    for (const std::vector<Pass> *v : {&p->passes, &p->scratch_passes}) {
+        for (const Pass &ps : *v) {
+            const hipError_t e = ps.swap ? launch_swap(p->eb, ps.wp, 1, nullptr)
+                                         : launch_stage(p->eb, ps.layout, ps.logl, ps.lines, ps.sets, ps.sp, nullptr);
+            if (e != hipSuccess) ok = false;
+        }
+    }
+    set_dry_run(false);
+    return ok;
+}
+
+// A caller-chosen decomposition: log2 digits summing to q, each strided
+// digit within the strided kernels' range [4, col_max], a one-digit plan
+// within the row kernels' range, and palindromic for an in-place plan (the
+// digit-reversal swap needs it).
+bool digits_usable(int q, int eb, int inplace, const int *d, int m)
+{
+    if (m < 1 || m > MAX_DIGITS) return false;
+    int sum = 0;
+    for (int i = 0; i < m; ++i) sum += d[i];
+    if (sum != q) return false;
+    if (m == 1) return q <= row_max(eb);
+    for (int i = 0; i < m; ++i) {
+        if (d[i] < 4 || d[i] > col_max(eb)) return false;
+        if (inplace && d[i] != d[m - 1 - i]) return false;
+    }
+    return true;
+}
+
+efft_plan_s *create_c2c(int64_t n, int64_t batch, int dtype, int dir, int inplace, double scale, int *status,
+                        const int *digits = nullptr, int ndigits = 0)
 {
     efft_plan_s *p = new (std::nothrow) efft_plan_s();
     if (!p) {
@@ -562,11 +597,30 @@ efft_plan_s *create_c2c(int64_t n, int64_t batch, int dtype, int dir, int inplac
     p->scale = scale;
     p->kind = KIND_C2C;
     p->inner = nullptr;
-    p->m = plan_digits(p->q, p->eb, p->inplace, p->digits);
+    if (digits) {
+        if (!digits_usable(p->q, p->eb, p->inplace, digits, ndigits)) {
+            delete p;
+            *status = EFFT_ERR_ARG;
+            return nullptr;
+        }
+        p->m = ndigits;
+        for (int i = 0; i < ndigits; ++i) p->digits[i] = digits[i];
+    } else {
+        p->m = plan_digits(p->q, p->eb, p->inplace, p->digits);
+    }
     if (p->m < 1) {
         delete p;
         *status = EFFT_ERR_SIZE;
         return nullptr;
+    }
+    if (digits) {  // a kernel must exist for every pass of a chosen decomposition
+        TwTable none{};
+        build_passes(p, none);
+        if (!kernels_exist(p)) {
+            delete p;
+            *status = EFFT_ERR_ARG;
+            return nullptr;
+        }
     }
     TwTable tt{};
     *status = make_tables(p, p->q, &tt);
@@ -576,6 +630,17 @@ efft_plan_s *create_c2c(int64_t n, int64_t batch, int dtype, int dir, int inplac
     }
     build_passes(p, tt);
     return p;
+}
+
+// tile counts of a sub-FFT pass for `lines` x `sets` lines per workgroup;
+// -1 if tiles would straddle blocks or the lines do not divide evenly
+int64_t tiles_for(const efft_plan_s *p, const Pass &ps, int lines, int sets)
+{
+    const int64_t nlines = p->n >> ps.logl;  // lines per signal
+    const int64_t w = int64_t(lines) * sets;
+    if (w < 1 || nlines % w) return -1;
+    if (ps.layout == LAYOUT_COL && ps.sp.s % w) return -1;  // a tile stays inside one block
+    return nlines / w * p->batch;
 }
 
 void free_plan(efft_plan_s *p)
@@ -864,6 +929,83 @@ int64_t efft_plan_bytes(const efft_plan_t *plan)
     const efft_plan_s *p = live(plan);
     if (!p) return -1;
     return p->table_bytes + (p->inner ? p->inner->table_bytes : 0) + (p->inner2 ? p->inner2->table_bytes : 0);
+}
+
+efft_plan_t *efft_plan_digits(int64_t n, int64_t batch, int dtype, int dir, int inplace, double scale,
+                              const int *log2_digits, int m)
+{
+    const int q = log2_exact(n);
+    int status = validate_args(q, dtype, dir, scale);
+    if (status == EFFT_OK && (batch < 1 || !log2_digits)) status = batch < 1 ? EFFT_ERR_ARG : EFFT_ERR_NULLPTR;
+    if (status == EFFT_OK && batch > (int64_t(1) << 40) / n) status = EFFT_ERR_SIZE;
+    if (status != EFFT_OK) {
+        g_last_error = status;
+        return nullptr;
+    }
+    efft_plan_s *p = create_c2c(n, batch, dtype, dir, inplace, scale, &status, log2_digits, m);
+    if (!p) {
+        g_last_error = status;
+        return nullptr;
+    }
+    register_plan(p);
+    g_last_error = EFFT_OK;
+    return p;
+}
+
+int efft_pass_options(const efft_plan_t *plan, int scratch, int pass, int *opts)
+{
+    const efft_plan_s *p = live(plan);
+    if (!p) return plan ? EFFT_ERR_BADPLAN : EFFT_ERR_NULLPTR;
+    if (!opts) return EFFT_ERR_NULLPTR;
+    if (p->kind != KIND_C2C) return EFFT_ERR_PLAN_KIND;
+    const std::vector<Pass> &v = scratch ? p->scratch_passes : p->passes;
+    if (pass < 0 || pass >= int(v.size())) return EFFT_ERR_ARG;
+    const Pass &ps = v[size_t(pass)];
+    if (ps.swap) {
+        opts[0] = -1;
+        opts[1] = opts[2] = opts[3] = 0;
+        opts[4] = opts[5] = ps.wp.nt_hint;
+    } else {
+        opts[0] = ps.layout;
+        opts[1] = ps.lines;
+        opts[2] = ps.sets;
+        opts[3] = ps.sp.order;
+        opts[4] = ps.sp.nt_load;
+        opts[5] = ps.sp.nt_store;
+    }
+    return EFFT_OK;
+}
+
+int efft_set_pass_options(efft_plan_t *plan, int scratch, int pass, const int *opts)
+{
+    efft_plan_s *p = const_cast<efft_plan_s *>(live(plan));
+    if (!p) return plan ? EFFT_ERR_BADPLAN : EFFT_ERR_NULLPTR;
+    if (!opts) return EFFT_ERR_NULLPTR;
+    if (p->kind != KIND_C2C) return EFFT_ERR_PLAN_KIND;
+    std::vector<Pass> &v = scratch ? p->scratch_passes : p->passes;
+    if (pass < 0 || pass >= int(v.size())) return EFFT_ERR_ARG;
+    for (int i = 3; i < 6; ++i)
+        if (opts[i] < 0) return EFFT_ERR_ARG;
+    if (opts[3] > TILE_XCD_SCATTER || opts[4] > 1 || opts[5] > 1) return EFFT_ERR_ARG;
+    Pass ps = v[size_t(pass)];
+    if (ps.swap) {
+        ps.wp.nt_hint = opts[4];
+    } else {
+        const int64_t nt = tiles_for(p, ps, opts[1], opts[2]);
+        if (nt < 0) return EFFT_ERR_ARG;
+        ps.lines = opts[1];
+        ps.sets = opts[2];
+        ps.sp.ntiles = nt;
+        ps.sp.order = opts[3];
+        ps.sp.nt_load = opts[4];
+        ps.sp.nt_store = opts[5];
+        set_dry_run(true);
+        const hipError_t e = launch_stage(p->eb, ps.layout, ps.logl, ps.lines, ps.sets, ps.sp, nullptr);
+        set_dry_run(false);
+        if (e != hipSuccess) return EFFT_ERR_ARG;  // no kernel for this combination
+    }
+    v[size_t(pass)] = ps;
+    return EFFT_OK;
 }
 
 int64_t efft_plan_batch(const efft_plan_t *plan)

@@ -117,3 +117,29 @@ def test_binding_refuses_cpu_tensors():
     from paper_1409_5757_amd import api
     with pytest.raises(ValueError):
         api.fft(torch.zeros(16, dtype=torch.complex64))
+
+
+def test_plan_digits_rejects_unusable_decompositions(lib):
+    """Checked before any device work (CPU)."""
+    def mk(n, inplace, digits):
+        arr = (ctypes.c_int * len(digits))(*digits)
+        return lib.efft_plan_digits(n, 1, C128, -1, inplace, 1.0, arr, len(digits))
+    assert mk(1 << 20, 1, [8, 12]) is None and lib.efft_last_error() == -11      # not a palindrome
+    assert mk(1 << 20, 0, [10, 9]) is None and lib.efft_last_error() == -11      # sum != q
+    assert mk(1 << 20, 0, [3, 17]) is None and lib.efft_last_error() == -11      # digit out of range
+    assert mk(1 << 13, 0, [13]) is None and lib.efft_last_error() == -11         # one digit > 12
+    assert mk(1 << 30, 1, [5, 5, 5, 5, 5, 5, 0]) is None and lib.efft_last_error() == -11  # too many
+    assert lib.efft_plan_digits(1 << 20, 1, C128, -1, 1, 1.0, None, 2) is None
+    assert lib.efft_last_error() == -4
+    assert lib.efft_pass_options(None, 0, 0, None) == -4
+    assert lib.efft_set_pass_options(None, 0, 0, None) == -4
+
+
+def test_tuner_decompositions():
+    from paper_1409_5757_amd import tune
+    assert tune.decompositions(12, True) == [[12]]
+    d30 = tune.decompositions(30, True)
+    assert [10, 10, 10] in d30 and all(x == x[::-1] and sum(x) == 30 for x in d30)
+    assert all(4 <= v <= 10 for x in d30 for v in x)
+    d32 = tune.decompositions(32, False)
+    assert [8, 8, 8, 8] in d32 and [10, 10, 6, 6] in d32

@@ -1,0 +1,73 @@
+"""Tuning: launch options never change the arithmetic (bit-identical results
+for every option the tuner tries), tuned decompositions stay within the
+oracle tolerance, and wisdom entries round-trip through a file."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1409_5757_amd import api, tune
+from tests.gpu_util import TOL, host_input, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("q,dtype,inplace", [(20, torch.complex128, True), (22, torch.complex64, False),
+                                             (14, torch.complex128, False)])
+def test_every_option_gives_identical_bits(q, dtype, inplace):
+    n = 1 << q
+    xh = host_input("uniform", 40 + q, n, dtype)
+    ref_plan = api.Plan(n, dtype, -1, inplace, device=torch.device("cuda", 0))
+    ref = ref_plan.execute(torch.from_numpy(xh).cuda())
+    p = tune.make_plan(n, dtype, inplace)
+    tried = 0
+    for i in range(p.passes):
+        cur = tune._options(p, False, i)
+        cands = ([[-1, 0, 0, 0, a, a] for a in (0, 1)] if cur[0] == -1 else
+                 [[cur[0], w, s, o, a, b] for w in tune.LINE_CHOICES for s in (1, 2) for o in (0, 1, 2)
+                  for a, b in tune.HINT_CHOICES])
+        for c in cands:
+            if not tune._set_options(p, False, i, c):
+                continue
+            tried += 1
+            got = p.execute(torch.from_numpy(xh).cuda())
+            assert torch.equal(got, ref), (i, c)
+        tune._set_options(p, False, i, cur)
+    print(f"q={q}: {tried} option settings, all bit-identical", flush=True)
+    assert tried >= p.passes
+
+
+def test_tune_and_wisdom_round_trip():
+    n, dtype = 1 << 20, torch.complex64
+    entry = tune.tune(n, dtype, True, reps=1, max_digits=3)
+    assert sum(entry["digits"]) == 20 and entry["ms"] > 0 and entry["default_ms"] > 0
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "wisdom.json")
+        k = tune.key(n, dtype, True)
+        tune.save(path, {k: entry})
+        back = tune.load(path)[k]
+    assert back == entry
+    p = tune.plan(n, dtype, True, back)
+    xh = host_input("normal", 5, n, dtype)
+    x = torch.from_numpy(xh).cuda()
+    p.execute(x)
+    assert rel_l2(x.cpu().numpy(), oracle.fft(xh)) <= TOL[dtype]
+    for i, opts in enumerate(back["passes"]):
+        assert tune._options(p, False, i) == opts
+
+
+def test_forced_decompositions_match_oracle():
+    for n, dtype, inplace, digits in [(1 << 20, torch.complex128, True, [5, 10, 5]),
+                                      (1 << 20, torch.complex128, False, [4, 8, 8]),
+                                      (1 << 24, torch.complex64, True, [6, 6, 6, 6]),
+                                      (1 << 24, torch.complex64, False, [10, 4, 10])]:
+        p = tune.make_plan(n, dtype, inplace, digits)
+        xh = host_input("uniform", 9, n, dtype)
+        x = torch.from_numpy(xh).cuda()
+        y = p.execute(x)
+        err = rel_l2(y.cpu().numpy(), oracle.fft(xh))
+        print(f"n=2^{n.bit_length() - 1} digits={digits}: rel_l2={err:.2e}", flush=True)
+        assert err <= TOL[dtype]
