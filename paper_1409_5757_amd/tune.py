@@ -57,7 +57,8 @@ def decompositions(q: int, inplace: bool, max_digits: int = 4) -> list[list[int]
         for d in itertools.product(range(4, 11), repeat=m):
             if sum(d) == q and (not inplace or d == d[::-1]):
                 out.append(list(d))
-    out.sort(key=lambda d: (len(d), -min(d)))
+    # fewest passes first, then the most balanced (the planner's own preference)
+    out.sort(key=lambda d: (len(d), max(d) - min(d), d))
     return out
 
 
@@ -151,7 +152,8 @@ def tune_passes(plan: api.Plan, x, scratch_buf=None, reps: int = 3) -> tuple[lis
 
 
 def tune(n: int, dtype: torch.dtype, inplace: bool, batch: int = 1, scratch: bool = False,
-         reps: int = 3, max_digits: int = 4, search_digits: bool = True, log=None) -> dict:
+         reps: int = 3, max_digits: int = 4, search_digits: bool = True, log=None,
+         max_candidates: int = 6) -> dict:
     """Measure and return a wisdom entry {"digits", "passes", "ms", "default_ms"}."""
     dev = torch.device("cuda", 0)
     x = torch.empty(batch * n, dtype=dtype, device=dev)
@@ -169,7 +171,7 @@ def tune(n: int, dtype: torch.dtype, inplace: bool, batch: int = 1, scratch: boo
     cands = decompositions(q, inplace, max_digits) if search_digits else [default_digits]
     if default_digits in cands:  # the planner's choice first
         cands.remove(default_digits)
-    cands.insert(0, default_digits)
+    cands = [default_digits] + cands[:max(0, max_candidates - 1)]
     best = None
     for d in cands:
         try:
@@ -226,11 +228,12 @@ def main(argv=None) -> int:
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--max-digits", type=int, default=4)
+    ap.add_argument("--max-candidates", type=int, default=6)
     ap.add_argument("--out", default="wisdom.json")
     a = ap.parse_args(argv)
     n, dt = 1 << a.log2n, _DT[a.dtype]
     entry = tune(n, dt, a.inplace or a.scratch, a.batch, a.scratch, a.reps, a.max_digits,
-                 log=lambda s: print(s, flush=True))
+                 log=lambda s: print(s, flush=True), max_candidates=a.max_candidates)
     w = load(a.out)
     w[key(n, dt, a.inplace or a.scratch, a.batch, a.scratch)] = entry
     save(a.out, w)
