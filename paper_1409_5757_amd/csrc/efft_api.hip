@@ -171,7 +171,7 @@ struct efft_plan_s {
     int64_t m_pad;
     efft_plan_s *inner2;
     double2 *chirp;
-    void *vhat, *work;
+    void *vhat, *work, *work2;  // work2: second work array of out-of-place inner plans
 };
 
 namespace {
@@ -429,11 +429,13 @@ int run_chirp(const efft_plan_s *p, const void *in, void *out, hipStream_t strea
         char *y = static_cast<char *>(out) + b * p->n * p->eb;
         if (!rec(0) || launch_premul(p->eb, x, p->work, p->chirp, p->n, p->m_pad, stream) != hipSuccess)
             return EFFT_ERR_HIP;
-        int r = run_c2c(p->inner, p->work, p->work, stream, events ? events + 1 : nullptr, events ? nf + 1 : 0);
+        // out-of-place inner plans (when the device has room): work -> work2 -> work
+        void *mid = p->work2 ? p->work2 : p->work;
+        int r = run_c2c(p->inner, p->work, mid, stream, events ? events + 1 : nullptr, events ? nf + 1 : 0);
         if (r != EFFT_OK) return r;
-        if (!rec(nf + 1) || launch_pointwise(p->eb, p->work, p->vhat, p->m_pad, stream) != hipSuccess)
+        if (!rec(nf + 1) || launch_pointwise(p->eb, mid, p->vhat, p->m_pad, stream) != hipSuccess)
             return EFFT_ERR_HIP;
-        r = run_c2c(p->inner2, p->work, p->work, stream, events ? events + nf + 2 : nullptr, events ? nb + 1 : 0);
+        r = run_c2c(p->inner2, mid, p->work, stream, events ? events + nf + 2 : nullptr, events ? nb + 1 : 0);
         if (r != EFFT_OK) return r;
         if (!rec(nf + nb + 2) || launch_postmul(p->eb, p->work, y, p->chirp, p->n, p->scale, stream) != hipSuccess)
             return EFFT_ERR_HIP;
@@ -651,6 +653,7 @@ void free_plan(efft_plan_s *p)
     if (p->chirp) (void)hipFree(p->chirp);
     if (p->vhat) (void)hipFree(p->vhat);
     if (p->work) (void)hipFree(p->work);
+    if (p->work2) (void)hipFree(p->work2);
     free_plan(p->inner);
     free_plan(p->inner2);
     delete p;
@@ -679,24 +682,39 @@ efft_plan_s *create_chirp(int64_t n, int64_t batch, int dtype, int dir, int inpl
     p->scale = scale;
     p->kind = KIND_CHIRP;
     p->m_pad = m;
-    p->inner = create_c2c(m, 1, dtype, EFFT_FORWARD, 1, 1.0, status);
-    if (p->inner) p->inner2 = create_c2c(m, 1, dtype, EFFT_BACKWARD, 1, 1.0, status);
+    // Out-of-place M-point plans need fewer passes (no digit-reversal pass,
+    // no palindrome constraint) but a second work array: used when the three
+    // M-point arrays and the chirp take at most half of the device's memory,
+    // a fixed rule per device so that results do not depend on what else is
+    // allocated.
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        total_b = 0;
+    }
+    const bool oop = double(3 * m * int64_t(dtype_bytes(dtype)) + n * int64_t(sizeof(double2))) <= 0.5 * double(total_b);
+    p->inner = create_c2c(m, 1, dtype, EFFT_FORWARD, oop ? 0 : 1, 1.0, status);
+    if (p->inner) p->inner2 = create_c2c(m, 1, dtype, EFFT_BACKWARD, oop ? 0 : 1, 1.0, status);
     if (!p->inner || !p->inner2) {
         free_plan(p);
         return nullptr;
     }
     const size_t eb = size_t(p->eb);
     if (hipMalloc(reinterpret_cast<void **>(&p->chirp), size_t(n) * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&p->vhat, size_t(m) * eb) != hipSuccess || hipMalloc(&p->work, size_t(m) * eb) != hipSuccess) {
+        hipMalloc(&p->vhat, size_t(m) * eb) != hipSuccess || hipMalloc(&p->work, size_t(m) * eb) != hipSuccess ||
+        (oop && hipMalloc(&p->work2, size_t(m) * eb) != hipSuccess)) {
         (void)hipGetLastError();
         free_plan(p);
         *status = EFFT_ERR_ALLOC;
         return nullptr;
     }
-    p->table_bytes = int64_t(n) * int64_t(sizeof(double2)) + 2 * m * int64_t(eb);
+    p->table_bytes = int64_t(n) * int64_t(sizeof(double2)) + (oop ? 3 : 2) * m * int64_t(eb);
+    // V = DFT_M(v) / M, formed in the work array and transformed into vhat
+    // (in place when the inner plans are)
+    void *vsrc = oop ? p->work : p->vhat;
     if (launch_chirp(p->chirp, n, dir, nullptr) != hipSuccess ||
-        launch_chirp_v(p->eb, p->vhat, p->chirp, n, m, nullptr) != hipSuccess ||
-        run_c2c(p->inner, p->vhat, p->vhat, nullptr, nullptr, 0) != EFFT_OK || hipDeviceSynchronize() != hipSuccess) {
+        launch_chirp_v(p->eb, vsrc, p->chirp, n, m, nullptr) != hipSuccess ||
+        run_c2c(p->inner, vsrc, p->vhat, nullptr, nullptr, 0) != EFFT_OK || hipDeviceSynchronize() != hipSuccess) {
         free_plan(p);
         *status = EFFT_ERR_HIP;
         return nullptr;
