@@ -89,8 +89,12 @@ enum {
  * tables on the current device and waits for that to finish.  Returns NULL on
  * failure, with the reason in efft_last_error().
  *
- * A length that is not a power of two (the paper's EFFT takes N = M * 2^s,
- * Section 2.2 and Section 4, with MKL doing the M-point bin DFTs) is
+ * A length N = M * 2^s with an odd M <= 15 (the paper's EFFT takes N =
+ * M * 2^s, Section 2.2 and Section 4, with MKL doing the M-point bin DFTs)
+ * runs one radix-M pass (direct M-point sums in FP64 and the twiddle
+ * W_N^{n2 k1}), the M batched 2^s-point transforms of the rows and one
+ * reorder pass; such a plan owns the tables and a work array of N points
+ * per signal.  Any other length is
  * transformed through the chirp identity n*k = (n^2 + k^2 - (k-n)^2)/2:
  * F_k = a_k sum_n (x_n a_n) conj(a_{k-n}), a_m = exp(sign*pi*i*m^2/N), a
  * linear convolution done as a cyclic one of length M = 2^ceil(log2(2N-1))

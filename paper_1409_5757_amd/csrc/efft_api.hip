@@ -144,7 +144,7 @@ int dtype_bytes(int dtype) { return dtype == EFFT_C128 ? 16 : dtype == EFFT_C64 
 
 }  // namespace
 
-enum PlanKind { KIND_C2C = 0, KIND_R2C = 1, KIND_C2R = 2, KIND_CHIRP = 3 };
+enum PlanKind { KIND_C2C = 0, KIND_R2C = 1, KIND_C2R = 2, KIND_CHIRP = 3, KIND_MIXED = 4 };
 
 struct efft_plan_s {
     uint64_t magic;
@@ -172,6 +172,10 @@ struct efft_plan_s {
     efft_plan_s *inner2;
     double2 *chirp;
     void *vhat, *work, *work2;  // work2: second work array of out-of-place inner plans
+    // N = M * 2^s with a small odd M (KIND_MIXED): tables (W_M, lo, hi of W_N)
+    // in `tables`, rows of 2^s points transformed by `inner` (batch M), work
+    int m_odd, h_mixed;
+    int64_t cols;
 };
 
 namespace {
@@ -411,7 +415,32 @@ int total_passes(const efft_plan_s *p)
     if (p->kind == KIND_C2C) return int(p->passes.size());
     if (p->kind == KIND_CHIRP)  // premul, M-point forward, product, M-point backward, postmul
         return int(p->inner->passes.size()) + int(p->inner2->passes.size()) + 3;
+    if (p->kind == KIND_MIXED)  // radix-M pass, the rows' passes, reorder
+        return int(p->inner->passes.size()) + 2;
     return int(p->inner->passes.size()) + 1;
+}
+
+// N = M * 2^s: radix-M pass into the work array, the batched 2^s-point rows
+// in place on it, reorder into natural order (times scale).
+int run_mixed(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events, int nevents)
+{
+    const int np = total_passes(p);
+    if (events && nevents < np + 1) return EFFT_ERR_ARG;
+    auto rec = [&](int i) {
+        return !events || hipEventRecord(static_cast<hipEvent_t>(events[i]), stream) == hipSuccess;
+    };
+    const int64_t n_lo = int64_t(1) << p->h_mixed;
+    const double2 *wm = p->tables, *lo = p->tables + p->m_odd, *hi = lo + n_lo;
+    if (!rec(0) || launch_radix_m(p->eb, p->m_odd, in, p->work, wm, lo, hi, p->h_mixed, p->cols, p->batch,
+                                  p->dir == EFFT_BACKWARD ? 1 : 0, stream) != hipSuccess)
+        return EFFT_ERR_HIP;
+    const int ni = int(p->inner->passes.size());
+    const int r = run_c2c(p->inner, p->work, p->work, stream, events ? events + 1 : nullptr, events ? ni + 1 : 0);
+    if (r != EFFT_OK) return r;
+    if (!rec(ni + 1) ||
+        launch_reorder_m(p->eb, p->m_odd, p->work, out, p->cols, p->batch, p->scale, stream) != hipSuccess)
+        return EFFT_ERR_HIP;
+    return rec(np) ? EFFT_OK : EFFT_ERR_HIP;
 }
 
 // Chirp plan: per signal, w = (x a) zero-padded; w = DFT_M(w); w *= V;
@@ -449,6 +478,7 @@ int run(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, voi
 {
     if (p->kind == KIND_C2C) return run_c2c(p, in, out, stream, events, nevents);
     if (p->kind == KIND_CHIRP) return run_chirp(p, in, out, stream, events, nevents);
+    if (p->kind == KIND_MIXED) return run_mixed(p, in, out, stream, events, nevents);
     const int np = total_passes(p);
     if (events && nevents < np + 1) return EFFT_ERR_ARG;
     const int64_t h = p->n / 2;
@@ -659,6 +689,58 @@ void free_plan(efft_plan_s *p)
     delete p;
 }
 
+// Plan for N = M * 2^s, M odd and 3 <= M <= 15: the two tables, a work array
+// of batch * N points and the batched plan of the 2^s-point rows.
+efft_plan_s *create_mixed(int64_t n, int64_t batch, int dtype, int dir, int inplace, double scale, int *status)
+{
+    int64_t cols = 1;
+    while ((n / cols) % 2 == 0) cols *= 2;
+    const int mo = int(n / cols);
+    efft_plan_s *p = new (std::nothrow) efft_plan_s();
+    if (!p) {
+        *status = EFFT_ERR_ALLOC;
+        return nullptr;
+    }
+    p->magic = PLAN_MAGIC;
+    p->n = n;
+    p->batch = batch;
+    p->q = -1;
+    p->dtype = dtype;
+    p->dir = dir;
+    p->inplace = inplace ? 1 : 0;
+    p->eb = dtype_bytes(dtype);
+    p->scale = scale;
+    p->kind = KIND_MIXED;
+    p->m_odd = mo;
+    p->cols = cols;
+    int bits = 0;
+    while ((int64_t(1) << bits) < n) ++bits;
+    p->h_mixed = (bits + 1) / 2;
+    const int64_t n_lo = int64_t(1) << p->h_mixed, n_hi = (n + n_lo - 1) / n_lo;
+    p->inner = create_c2c(cols, batch * mo, dtype, dir, 1, 1.0, status);
+    if (!p->inner) {
+        free_plan(p);
+        return nullptr;
+    }
+    p->table_bytes = (mo + n_lo + n_hi) * int64_t(sizeof(double2)) + batch * n * p->eb;
+    if (hipMalloc(reinterpret_cast<void **>(&p->tables), size_t(mo + n_lo + n_hi) * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->work, size_t(batch * n) * size_t(p->eb)) != hipSuccess) {
+        (void)hipGetLastError();
+        free_plan(p);
+        *status = EFFT_ERR_ALLOC;
+        return nullptr;
+    }
+    if (launch_mixed_tables(p->tables, mo, p->tables + mo, n_lo, p->tables + mo + n_lo, n_hi, p->h_mixed, n,
+                            nullptr) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        free_plan(p);
+        *status = EFFT_ERR_HIP;
+        return nullptr;
+    }
+    *status = EFFT_OK;
+    return p;
+}
+
 // Plan for a length n >= 3 that is not a power of two: two in-place plans of
 // M = 2^ceil(log2(2n - 1)) points, the chirp and the transformed kernel are
 // built here (on the current device), once.
@@ -783,8 +865,12 @@ efft_plan_t *efft_plan_many(int64_t n, int64_t batch, int dtype, int dir, int in
         g_last_error = status;
         return nullptr;
     }
-    efft_plan_s *p = chirp ? create_chirp(n, batch, dtype, dir, inplace, scale, &status)
-                           : create_c2c(n, batch, dtype, dir, inplace, scale, &status);
+    int64_t odd = n;
+    while (odd > 0 && odd % 2 == 0) odd /= 2;
+    const bool mixed = chirp && odd <= 15;  // N = M * 2^s with a small odd M: one radix-M pass
+    efft_plan_s *p = mixed   ? create_mixed(n, batch, dtype, dir, inplace, scale, &status)
+                     : chirp ? create_chirp(n, batch, dtype, dir, inplace, scale, &status)
+                             : create_c2c(n, batch, dtype, dir, inplace, scale, &status);
     if (!p) {
         g_last_error = status;
         return nullptr;

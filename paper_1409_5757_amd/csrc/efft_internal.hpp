@@ -122,6 +122,15 @@ hipError_t launch_pointwise(int dtype_bytes, void *w, const void *v, int64_t m, 
 // out[0..n) = scale * a * w
 hipError_t launch_postmul(int dtype_bytes, const void *w, void *out, const double2 *a, int64_t n, double scale,
                           hipStream_t stream);
+// lengths N = M * 2^s with a small odd M (efft_mixed.hip): tables W_M^j and
+// the two-level W_N table; the radix-M pass (x -> w) and the reorder pass
+// (w -> out, times scale), for `batch` contiguous signals
+hipError_t launch_mixed_tables(double2 *wm, int m, double2 *lo, int64_t n_lo, double2 *hi, int64_t n_hi, int h,
+                               int64_t n, hipStream_t stream);
+hipError_t launch_radix_m(int dtype_bytes, int m, const void *x, void *w, const double2 *wm, const double2 *lo,
+                          const double2 *hi, int h, int64_t cols, int64_t batch, int conj, hipStream_t stream);
+hipError_t launch_reorder_m(int dtype_bytes, int m, const void *w, void *out, int64_t cols, int64_t batch,
+                            double scale, hipStream_t stream);
 // while on (per host thread), launch_stage / launch_swap only check that a
 // kernel exists for the arguments and launch nothing
 void set_dry_run(bool on);

@@ -84,3 +84,52 @@ def test_plan_reports_memory_and_passes():
     # chirp (FP64) + V + work of M = 2048 points, plus the two inner plans' tables
     assert p.device_bytes() >= 1000 * 16 + 2 * 2048 * 16
     assert p.passes >= 5 and p.scratch_bytes == 0
+
+
+MIXED = [(m, s) for m in (3, 5, 7, 9, 11, 13, 15) for s in (0, 1, 4, 7, 10)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_small_odd_factor_every_bin(dtype):
+    """N = M * 2^s with M odd and <= 15 takes the radix-M pass + power-of-two
+    rows + reorder: every bin against the direct sum."""
+    for i, (m, s) in enumerate(MIXED):
+        n = m << s
+        if n < 3:
+            continue
+        x = host_input("normal", 7000 + n, n, dtype)
+        direction = -1 if i % 2 == 0 else 1
+        inplace = i % 3 == 1
+        got, after = run_library(x, dtype, direction, inplace)
+        err = rel_l2(got, oracle.dft(x, direction))
+        assert err <= TOL[dtype], (m, s, err)
+        if after is not None:
+            np.testing.assert_array_equal(after, x)
+    print(f"{len(MIXED)} sizes M * 2^s within {TOL[dtype]}", flush=True)
+
+
+@pytest.mark.parametrize("dtype,n", [(torch.complex128, 3 << 26), (torch.complex64, 15 << 24),
+                                     (torch.complex128, 7 << 20), (torch.complex64, 13 << 21)])
+def test_small_odd_factor_sampled_large(dtype, n):
+    x = torch.from_numpy(host_input("uniform", 23, n, dtype)).cuda()
+    y = api.fft(x)
+    bins = sample_bins(n, 24, seed=n % 997)
+    ref = oracle_bins_from_device(x, bins)
+    scale = float(torch.linalg.vector_norm(x.to(torch.complex128)))
+    err = float(np.max(np.abs(y[torch.from_numpy(bins).cuda()].cpu().numpy() - ref))) / scale
+    print(f"n={n} {dtype}: max bin error / rms = {err:.2e}", flush=True)
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_small_odd_factor_batch_and_placement_bitwise(dtype):
+    for n in (3 << 12, 9 << 9, 15):
+        x = torch.from_numpy(np.stack([host_input("uniform", 80 + r, n, dtype) for r in range(5)])).cuda()
+        y = api.fft(x)
+        for r in range(5):
+            assert torch.equal(api.fft(x[r].contiguous()), y[r])
+        w = x.clone()
+        api.fft(w, inplace=True)
+        assert torch.equal(w, y)
+        z = api.ifft(y)
+        assert rel_l2(z.cpu().numpy(), x.cpu().numpy()) < (1e-13 if dtype == torch.complex128 else 3e-6)
