@@ -177,6 +177,10 @@ def main() -> int:
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": traffic, "kernel_pass": dom},
         "hbm_GBps_whole_transform": round(passes * bytes_pass / (ms_events * 1e-3) / 1e9, 1),
+        # the paper's memory metric (Section 5.3): device memory of the
+        # transform = the array itself + the plan's tables
+        "memory": {"array_bytes": n * 16, "plan_bytes": plan.device_bytes(),
+                   "peak_allocated_bytes": int(torch.cuda.max_memory_allocated(dev))},
         "passes_detail": passes_out,
     }
     # the same plan with a scratch array of N elements (one pass fewer, 2x memory)
