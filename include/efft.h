@@ -94,7 +94,8 @@ enum {
  * runs one radix-M pass (direct M-point sums in FP64 and the twiddle
  * W_N^{n2 k1}), the M batched 2^s-point transforms of the rows and one
  * reorder pass; such a plan owns the tables and a work array of N points
- * per signal.  Any other length is
+ * per signal, so at most one execution of it may be in flight at a time.
+ * Any other length is
  * transformed through the chirp identity n*k = (n^2 + k^2 - (k-n)^2)/2:
  * F_k = a_k sum_n (x_n a_n) conj(a_{k-n}), a_m = exp(sign*pi*i*m^2/N), a
  * linear convolution done as a cyclic one of length M = 2^ceil(log2(2N-1))
@@ -231,6 +232,8 @@ int efft_plan_passes_scratch(const efft_plan_t *plan);
  * pass i and events[npass] after the last one, so that per-pass durations can
  * be read with hipEventElapsedTime.  nevents must be at least the number of
  * passes + 1 (efft_plan_passes, or efft_plan_passes_scratch with scratch).
+ * Chirp-path plans (lengths with an odd factor above 15) accept events only
+ * with a batch of 1 (else EFFT_ERR_ARG).
  */
 int efft_exec_events(const efft_plan_t *plan, const void *in, void *out, void *scratch, void *stream,
                      void **events, int nevents);
@@ -254,8 +257,8 @@ int64_t efft_plan_bytes(const efft_plan_t *plan);
 int efft_plan_passes(const efft_plan_t *plan);
 
 /*
- * Host-only description of the decomposition a plan would use (no device
- * needed).  Writes the digit sizes log2(R_1), ..., log2(R_m) of
+ * Host-only description of the decomposition a power-of-two plan would use
+ * (no device needed; other lengths return EFFT_ERR_SIZE).  Writes the digit sizes log2(R_1), ..., log2(R_m) of
  * N = R_1 * ... * R_m (R_1 is the digit of the slowest-varying input index,
  * transformed first) into log2_radix[0 .. m), at most max_digits of them, and
  * returns m, or a negative status for invalid arguments.  *passes receives the
