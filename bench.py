@@ -114,10 +114,28 @@ def cpu_baseline(budget_s: float = 12.0):
         t_total += time.perf_counter() - t0
         reps += 1
     per = t_total / reps
-    return {"value": round(5 * n * q / per / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.threads(lib),
-            "kind": "oracle",
-            "sample": f"{reps} forward transforms of N=2^{q} complex128 (uniform [-1,1)), "
-                      f"{per:.2f} s each; same 5N log2N count"}
+    out = {"value": round(5 * n * q / per / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.threads(lib),
+           "kind": "oracle",
+           "sample": f"{reps} forward transforms of N=2^{q} complex128 (uniform [-1,1)), "
+                     f"{per:.2f} s each; same 5N log2N count"}
+    # the same oracle on one thread at 2^20 (OpenMP thread count set through
+    # the runtime the oracle library uses)
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+        q1, n1 = 20, 1 << 20
+        x1 = x[:n1].copy()
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            oracle.fft(x1, -1, lib=lib)
+        per1 = (time.perf_counter() - t0) / 3
+        gomp.omp_set_num_threads(out["cores"])
+        out["single_thread"] = {"value": round(5 * n1 * q1 / per1 / 1e9, 3), "unit": "GFLOP/s",
+                                "sample": f"3 transforms of N=2^{q1}, {per1 * 1e3:.1f} ms each"}
+    except OSError:
+        pass
+    return out
 
 
 def main() -> int:

@@ -253,6 +253,10 @@ const char *efft_strerror(int status);
  * handle. */
 int64_t efft_plan_bytes(const efft_plan_t *plan);
 
+/* The same figure under the name of a workspace query: device bytes a plan
+ * owns and keeps for its whole life (it allocates nothing at execution). */
+int64_t efft_workspace_bytes(const efft_plan_t *plan);
+
 /* Number of kernel launches one execution enqueues; -1 for a bad handle. */
 int efft_plan_passes(const efft_plan_t *plan);
 

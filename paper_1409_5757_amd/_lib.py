@@ -71,6 +71,8 @@ def _bind(lib):
     lib.efft_strerror.restype = ctypes.c_char_p
     lib.efft_plan_bytes.argtypes = [vp]
     lib.efft_plan_bytes.restype = i64
+    lib.efft_workspace_bytes.argtypes = [vp]
+    lib.efft_workspace_bytes.restype = i64
     lib.efft_plan_passes.argtypes = [vp]
     lib.efft_plan_passes.restype = ci
     lib.efft_schedule.argtypes = [i64, ci, ci, ctypes.POINTER(ci), ci, ctypes.POINTER(ci)]

@@ -1112,6 +1112,8 @@ int efft_set_pass_options(efft_plan_t *plan, int scratch, int pass, const int *o
     return EFFT_OK;
 }
 
+int64_t efft_workspace_bytes(const efft_plan_t *plan) { return efft_plan_bytes(plan); }
+
 int64_t efft_plan_batch(const efft_plan_t *plan)
 {
     const efft_plan_s *p = live(plan);
