@@ -312,7 +312,7 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
                 ps.lines = row_lines(p->eb, d[j], n / L);
             } else {
                 ps.layout = LAYOUT_COL;
-                ps.lines = col_lines(p->eb, d[j], s, true);
+                ps.lines = col_lines(p->eb, d[j], s, true, true);
                 ps.sets = col_sets(p->eb, d[j], ps.lines, s);
                 ps.sp.order = col_order(s);
                 ps.sp.twmode = TW_OFFSET;
@@ -380,11 +380,11 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
         ps.swap = false;
         ps.logl = d[j];
         ps.layout = LAYOUT_COL;
-        ps.lines = col_lines(p->eb, d[j], C, true);
+        ps.lines = col_lines(p->eb, d[j], C, true, true);
         ps.sets = col_sets(p->eb, d[j], ps.lines, C);
-        ps.sp.order = col_order(C);
         const int64_t L = int64_t(1) << d[j];
         ps.sp = base_params(p, tt);
+        ps.sp.order = col_order(C);
         ps.sp.s = C;
         ps.sp.B = C * L;
         ps.sp.n_over_l = uint64_t(n / L);

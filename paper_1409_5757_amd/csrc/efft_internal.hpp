@@ -54,7 +54,7 @@ struct StageParams {
     void *dst;
     int64_t s;
     int64_t B;
-    int64_t ntiles;      // workgroups in the grid
+    int64_t ntiles;      // tiles of the pass (the grid has ntiles / PIPE workgroups)
     uint64_t n_over_l;   // N / L, scales the in-line Stockham twiddles
     uint64_t tw_scale;   // see TwMode
     int64_t row_mul;     // LAYOUT_COL2ROW: line o's row starts at row_mul * rev(o);
@@ -185,10 +185,20 @@ constexpr int64_t WIDE_TILE_STRIDE = int64_t(1) << 17;
 // faster from a 2^17-element stride up, the plain XCD order below it)
 inline int col_order(int64_t stride) { return stride >= WIDE_TILE_STRIDE ? TILE_XCD_SCATTER : TILE_XCD; }
 
-inline int col_lines(int dtype_bytes, int logl, int64_t stride, bool same_positions)
+// Lines per workgroup for complex64 lines of 1024 points at a small stride:
+// the 16-line tile fills the LDS, one workgroup per CU; an 8-line tile lets
+// two share a CU, so one computes while the other streams (measured on
+// gfx950, 2^30 complex64 in place: the stride-2^10 pass 3.92 -> 3.51 ms; the
+// same change loses at large strides and for complex128 or shorter lines).
+constexpr int C64_SHARED_LINES = 8;
+
+// lines per workgroup of a strided pass (column_pass: a LAYOUT_COL pass,
+// which reads and writes the same strided lines)
+inline int col_lines(int dtype_bytes, int logl, int64_t stride, bool same_positions, bool column_pass = false)
 {
     const int w = col_lines_max(dtype_bytes, logl);
     if (same_positions && stride >= WIDE_TILE_STRIDE && stride >= w) return w;
+    if (column_pass && dtype_bytes == 8 && logl == 10 && stride >= C64_SHARED_LINES) return C64_SHARED_LINES;
     return col_lines_min(dtype_bytes);
 }
 

@@ -586,6 +586,10 @@ static hipError_t dispatch_logl(int layout, int lines, int sets, const StagePara
             if constexpr (WMIN != WMAX) {
                 if (lines == WMIN && sets == 1) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL, EPC>(p, stream);
             }
+            if constexpr (EB == 8 && LOGL == 10 && C64_SHARED_LINES != WMIN && C64_SHARED_LINES != WMAX) {
+                if (lines == C64_SHARED_LINES && sets == 1)
+                    return launch_one<T, LOGL, C64_SHARED_LINES, 1, LAYOUT_COL, EPC>(p, stream);
+            }
         }
         if (layout == LAYOUT_COL2ROW && sets == 1) {
             if (lines == WMAX) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL2ROW, EPC>(p, stream);
