@@ -12,6 +12,10 @@ path, the paper's own real-input FP32 transform at the same N, a device-copy
 ceiling, and the FP64 CPU oracle timed on a bounded sample on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--log2n Q] [--no-fp32] [--no-real] [--no-cpu]
+    python bench.py --workload c1|c3|c4|c5    # the other workloads, one line each:
+        c1 2^20 complex128 out of place; c3 2^32 complex64 out of place;
+        c4 2^34 complex64 in place, forward + inverse; c5 64 x 2^24 complex64
+        forward + loss + adjoint backward through autograd
 """
 from __future__ import annotations
 
@@ -53,11 +57,16 @@ def traffic_record(workload_key: str, pass_index: int):
     return None if p is None else p.get("hbm_bytes")
 
 
-def time_transform(plan, x, steps: int, warmup: int, scratch=None):
-    """Warm up, then time exactly `steps` transforms; per-pass event times."""
+def time_transform(plan, x, steps: int, warmup: int, scratch=None, out=None):
+    """Warm up, then time exactly `steps` transforms (in place, or into `out`
+    for out-of-place plans); per-pass event times."""
     import torch
+    out = x if out is None else out
     for _ in range(warmup):
-        plan.execute(x, scratch=scratch)
+        if plan.inplace:
+            plan.execute(x, scratch=scratch)
+        else:
+            plan.execute(x, out=out)
     torch.cuda.synchronize()
     npass = plan.passes if scratch is None else plan.scratch_passes
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(npass + 1)] for _ in range(steps)]
@@ -67,7 +76,7 @@ def time_transform(plan, x, steps: int, warmup: int, scratch=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for row in evs:
-        plan.execute_events(x, x, [e.cuda_event for e in row], scratch=scratch)
+        plan.execute_events(x, out, [e.cuda_event for e in row], scratch=scratch)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per_pass = [sum(row[i].elapsed_time(row[i + 1]) for row in evs) / steps for i in range(npass)]
@@ -118,24 +127,144 @@ def cpu_baseline(budget_s: float = 12.0):
            "kind": "oracle",
            "sample": f"{reps} forward transforms of N=2^{q} complex128 (uniform [-1,1)), "
                      f"{per:.2f} s each; same 5N log2N count"}
-    # the same oracle on one thread at 2^20 (OpenMP thread count set through
-    # the runtime the oracle library uses)
+    # the same oracle on one thread at 2^20 and 2^24 (OpenMP thread count set
+    # through the runtime the oracle library uses)
     try:
         import ctypes
         gomp = ctypes.CDLL("libgomp.so.1")
-        q1, n1 = 20, 1 << 20
-        x1 = x[:n1].copy()
-        gomp.omp_set_num_threads(1)
-        t0 = time.perf_counter()
-        for _ in range(3):
-            oracle.fft(x1, -1, lib=lib)
-        per1 = (time.perf_counter() - t0) / 3
-        gomp.omp_set_num_threads(out["cores"])
-        out["single_thread"] = {"value": round(5 * n1 * q1 / per1 / 1e9, 3), "unit": "GFLOP/s",
-                                "sample": f"3 transforms of N=2^{q1}, {per1 * 1e3:.1f} ms each"}
     except OSError:
-        pass
+        return out
+    gomp.omp_set_num_threads(1)
+    single = []
+    for q1, reps1 in ((20, 3), (24, 1)):
+        x1 = x[:1 << q1].copy()
+        t0 = time.perf_counter()
+        for _ in range(reps1):
+            oracle.fft(x1, -1, lib=lib)
+        per1 = (time.perf_counter() - t0) / reps1
+        single.append({"value": round(5 * (1 << q1) * q1 / per1 / 1e9, 3), "unit": "GFLOP/s",
+                       "sample": f"{reps1} transform(s) of N=2^{q1}, {per1 * 1e3:.1f} ms each"})
+    gomp.omp_set_num_threads(out["cores"])
+    out["single_thread"] = single
     return out
+
+
+# The other workloads: name -> (description, log2 N, dtype name, in place, batch)
+OTHER_WORKLOADS = {
+    "c1": ("forward out-of-place 1D C2C FFT, N=2^20 complex128 (16 MiB), uniform [-1,1) inputs in HBM",
+           20, "complex128", False, 1),
+    "c3": ("forward out-of-place 1D C2C FFT, N=2^32 complex64 (32 GiB in, 32 GiB out), "
+           "standard normal inputs in HBM", 32, "complex64", False, 1),
+    "c4": ("forward then inverse in-place 1D C2C FFT, N=2^34 complex64 (128 GiB), uniform [-1,1) "
+           "inputs in HBM; a step is both transforms", 34, "complex64", True, 1),
+    "c5": ("64 signals of N=2^24 complex64 (8 GiB): y = FFT(x) through autograd, loss = sum |w*y - t|^2, "
+           "backward through the hand-written adjoint; a step is forward + loss + backward",
+           24, "complex64", False, 64),
+}
+
+
+def roofline(per_pass, bytes_pass):
+    dom = max(range(len(per_pass)), key=lambda i: per_pass[i])
+    achieved = bytes_pass / (per_pass[dom] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "kernel_pass": dom}
+
+
+def run_other(args) -> int:
+    """One JSON line for workload c1, c3, c4 or c5 (same keys as the default
+    line; per-pass times from the library's events on the launch stream)."""
+    import torch
+    from paper_1409_5757_amd import _lib, api, inputs
+
+    _lib.load()
+    label, q, dtn, inplace, batch = OTHER_WORKLOADS[args.workload]
+    dt = getattr(torch, dtn)
+    eb = 16 if dt == torch.complex128 else 8
+    n = 1 << q
+    dev = torch.device("cuda", 0)
+    bytes_pass = 2 * batch * n * eb
+    x = torch.empty((batch, n) if batch > 1 else (n,), dtype=dt, device=dev)
+    if args.workload == "c3":
+        inputs.fill_normal_torch(x, seed=0)
+    elif batch == 1:
+        inputs.fill_uniform_torch(x, seed=0)
+    flops = 5 * batch * n * q
+    extra = {}
+    if args.workload in ("c1", "c3"):
+        plan = api.Plan(n, dt, -1, False, device=dev)
+        y = torch.empty_like(x)
+        ms_step, _, per_pass = time_transform(plan, x, args.steps, args.warmup, out=y)
+        plan.close()
+    elif args.workload == "c4":
+        # forward, then the inverse (backward direction scaled by 2^-q, exact)
+        # (each step restores the data, so repeated steps stay in range)
+        pf = api.Plan(n, dt, -1, True, device=dev)
+        pi = api.Plan(n, dt, +1, True, scale=2.0 ** -q, device=dev)
+        for _ in range(args.warmup):
+            pf.execute(x)
+            pi.execute(x)
+        torch.cuda.synchronize()
+        ev = [[[torch.cuda.Event(enable_timing=True) for _ in range(p.passes + 1)] for p in (pf, pi)]
+              for _ in range(args.steps)]
+        for row in ev:
+            for e in row[0] + row[1]:
+                e.record()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for row in ev:
+            pf.execute_events(x, x, [e.cuda_event for e in row[0]])
+            pi.execute_events(x, x, [e.cuda_event for e in row[1]])
+        torch.cuda.synchronize()
+        ms_step, flops = (time.perf_counter() - t0) / args.steps * 1e3, 2 * flops
+        per_pass = [sum(r[d][i].elapsed_time(r[d][i + 1]) for r in ev) / args.steps
+                    for d, p in enumerate((pf, pi)) for i in range(p.passes)]
+        extra = {"forward_ms": round(sum(r[0][0].elapsed_time(r[0][-1]) for r in ev) / args.steps, 3),
+                 "inverse_ms": round(sum(r[1][0].elapsed_time(r[1][-1]) for r in ev) / args.steps, 3)}
+        pf.close()
+        pi.close()
+    else:
+        yt = torch.empty_like(x)
+        w = torch.empty(batch, n, dtype=torch.float32, device=dev)
+        for b in range(batch):
+            inputs.fill_normal_torch(x[b], seed=1000 + b)
+            inputs.fill_normal_torch(yt[b], seed=2000 + b)
+            inputs.fill_weights_torch(w[b], seed=3000 + b)
+        x.requires_grad_(True)
+
+        def step():
+            x.grad = None
+            f = api.fft(x)
+            torch.view_as_real(w * f - yt).pow(2).sum().backward()
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms_step, flops = (time.perf_counter() - t0) / args.steps * 1e3, 2 * flops
+        # per-pass times of the batched forward plan the step uses
+        pf = api.get_plan(n, dt, -1, False, 1.0, dev, batch)
+        xd = x.detach()
+        _, _, per_pass = time_transform(pf, xd, args.steps, 1, out=torch.empty_like(xd))
+        extra = {"transforms_per_step": 2, "forward_plan_ms_per_pass": [round(t, 4) for t in per_pass]}
+    result = {
+        "metric": METRIC, "value": round(flops / (ms_step * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if eb == 16 else "f32", "data": "synthetic",
+        "config": {"workload": label, "log2n": q, "batch": batch, "inplace": inplace,
+                   "digits_log2": _lib.schedule(n, 2 if eb == 16 else 1, inplace)[0]},
+        "roofline": roofline(per_pass, bytes_pass),
+        "passes_detail": [{"pass": i, "ms": round(t, 4), "GBps": round(bytes_pass / (t * 1e-3) / 1e9, 1)}
+                          for i, t in enumerate(per_pass)],
+        **extra,
+    }
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+    return 0
 
 
 def main() -> int:
@@ -148,11 +277,16 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-real", action="store_true")
     ap.add_argument("--no-anylen", action="store_true")
+    ap.add_argument("--workload", choices=sorted(OTHER_WORKLOADS) + ["c2"], default="c2",
+                    help="c2 (default): the in-place 2^30 complex128 transform with its companions; "
+                         "c1, c3, c4, c5: the other workloads, one JSON line each")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one transform on one GPU; runs on more than one GPU are not "
               "part of this benchmark (use --gpus 1)", file=sys.stderr)
         return 2
+    if args.workload != "c2":
+        return run_other(args)
 
     import torch
     from paper_1409_5757_amd import _lib, api, inputs
