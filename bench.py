@@ -399,11 +399,11 @@ def main() -> int:
     if not args.no_anylen:
         # lengths that are not powers of two (the paper's N = M * 2^s class):
         # N = 3 * 2^(q-2) takes one radix-3 pass, the power-of-two passes of
-        # the 2^(q-2)-point rows and a reorder pass; N = 2^(q-2) + 1 (no small
-        # odd factor) takes the chirp path.  GFLOP/s by the same nominal
-        # 5 N log2 N.
+        # the 2^(q-2)-point rows, the last written interleaved into the output;
+        # N = 2^(q-2) + 1 (no small odd factor) takes the chirp path.  GFLOP/s
+        # by the same nominal 5 N log2 N.
         for name, na, label in (("small_odd_factor", 3 << (q - 2),
-                                 f"forward in-place N=3*2^{q - 2} complex128 (radix-3 pass, 2^{q - 2}-point rows, reorder)"),
+                                 f"forward in-place N=3*2^{q - 2} complex128 (radix-3 pass, then the 2^{q - 2}-point rows, the last pass interleaving them)"),
                                 ("any_length", (1 << (q - 2)) + 1,
                                  f"forward in-place N=2^{q - 2}+1 complex128 (chirp path)")):
             xa = torch.empty(na, dtype=torch.complex128, device=dev)

@@ -92,8 +92,10 @@ enum {
  * A length N = M * 2^s with an odd M <= 15 (the paper's EFFT takes N =
  * M * 2^s, Section 2.2 and Section 4, with MKL doing the M-point bin DFTs)
  * runs one radix-M pass (direct M-point sums in FP64 and the twiddle
- * W_N^{n2 k1}), the M batched 2^s-point transforms of the rows and one
- * reorder pass; such a plan owns the tables and a work array of N points
+ * W_N^{n2 k1}) and the M batched 2^s-point transforms of the rows, whose last
+ * pass writes the rows interleaved into the output in natural order (rows of
+ * at most 2^12 points, which take a single pass, are followed by a reorder
+ * pass instead); such a plan owns the tables and a work array of N points
  * per signal, so at most one execution of it may be in flight at a time.
  * Any other length is
  * transformed through the chirp identity n*k = (n^2 + k^2 - (k-n)^2)/2:

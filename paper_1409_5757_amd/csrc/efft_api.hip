@@ -176,6 +176,10 @@ struct efft_plan_s {
     // in `tables`, rows of 2^s points transformed by `inner` (batch M), work
     int m_odd, h_mixed;
     int64_t cols;
+    // the rows' scratch schedule run in place on `work`, its last pass writing
+    // the rows interleaved into the output (natural order, times scale); empty
+    // when the rows take one pass (then a reorder pass follows them)
+    std::vector<Pass> mixed_passes;
 };
 
 namespace {
@@ -190,6 +194,7 @@ StageParams base_params(const efft_plan_s *p, const TwTable &tt)
     sp.scale = 1.0;
     sp.apply_scale = 0;
     sp.order = TILE_XCD;
+    sp.ilv = 1;
     return sp;
 }
 
@@ -409,19 +414,23 @@ int validate_ptr(const efft_plan_s *p, const void *ptr)
 
 int run_c2c(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events,
             int nevents);
+int run_passes(const std::vector<Pass> &passes, int64_t batch, int eb, const void *in, void *out,
+               void *scratch, hipStream_t stream, void **events, int nevents);
 
 int total_passes(const efft_plan_s *p)
 {
     if (p->kind == KIND_C2C) return int(p->passes.size());
     if (p->kind == KIND_CHIRP)  // premul, M-point forward, product, M-point backward, postmul
         return int(p->inner->passes.size()) + int(p->inner2->passes.size()) + 3;
-    if (p->kind == KIND_MIXED)  // radix-M pass, the rows' passes, reorder
-        return int(p->inner->passes.size()) + 2;
+    if (p->kind == KIND_MIXED)  // radix-M pass, the rows' passes (and a reorder)
+        return p->mixed_passes.empty() ? int(p->inner->passes.size()) + 2 : int(p->mixed_passes.size()) + 1;
     return int(p->inner->passes.size()) + 1;
 }
 
-// N = M * 2^s: radix-M pass into the work array, the batched 2^s-point rows
-// in place on it, reorder into natural order (times scale).
+// N = M * 2^s: radix-M pass into the work array, then the batched 2^s-point
+// rows in place on it; the rows' last pass writes them interleaved into the
+// output in natural order (times scale), or, for rows of one pass, a reorder
+// pass does.
 int run_mixed(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events, int nevents)
 {
     const int np = total_passes(p);
@@ -434,6 +443,9 @@ int run_mixed(const efft_plan_s *p, const void *in, void *out, hipStream_t strea
     if (!rec(0) || launch_radix_m(p->eb, p->m_odd, in, p->work, wm, lo, hi, p->h_mixed, p->cols, p->batch,
                                   p->dir == EFFT_BACKWARD ? 1 : 0, stream) != hipSuccess)
         return EFFT_ERR_HIP;
+    if (!p->mixed_passes.empty())  // in = scratch = work: the rows' passes in place, the last into out
+        return run_passes(p->mixed_passes, p->inner->batch, p->eb, p->work, out, p->work, stream,
+                          events ? events + 1 : nullptr, events ? np : 0);
     const int ni = int(p->inner->passes.size());
     const int r = run_c2c(p->inner, p->work, p->work, stream, events ? events + 1 : nullptr, events ? ni + 1 : 0);
     if (r != EFFT_OK) return r;
@@ -721,6 +733,23 @@ efft_plan_s *create_mixed(int64_t n, int64_t batch, int dtype, int dir, int inpl
     if (!p->inner) {
         free_plan(p);
         return nullptr;
+    }
+    if (!p->inner->scratch_passes.empty()) {
+        // the rows' scratch schedule with its last pass (rows written as
+        // columns at their natural positions) interleaving the M rows of each
+        // signal: bin k1 + M k2 = row k1, bin k2 lands at k2 * M + k1
+        p->mixed_passes = p->inner->scratch_passes;
+        Pass &last = p->mixed_passes.back();
+        if (last.swap || last.layout != LAYOUT_ROW2COL) {
+            free_plan(p);
+            *status = EFFT_ERR_HIP;
+            return nullptr;
+        }
+        last.sp.ilv = mo;
+        if (scale != 1.0) {
+            last.sp.apply_scale = 1;
+            last.sp.scale = scale;
+        }
     }
     p->table_bytes = (mo + n_lo + n_hi) * int64_t(sizeof(double2)) + batch * n * p->eb;
     if (hipMalloc(reinterpret_cast<void **>(&p->tables), size_t(mo + n_lo + n_hi) * sizeof(double2)) != hipSuccess ||

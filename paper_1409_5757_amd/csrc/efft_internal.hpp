@@ -59,6 +59,9 @@ struct StageParams {
     uint64_t tw_scale;   // see TwMode
     int64_t row_mul;     // LAYOUT_COL2ROW: line o's row starts at row_mul * rev(o);
                          // LAYOUT_ROW2COL: column stride of the output
+    int64_t ilv;         // LAYOUT_ROW2COL: signals interleaved in the output (1: none).
+                         // With ilv = M, bin k of signal b of each group of M signals
+                         // lands at k * M + b of that group's M * N outputs
     Digits rev;          // digits of o (COL2ROW), of blk (TW_REVBLOCK) or of the
                          // output column index (ROW2COL, whose source row is its reversal)
     TwTable tt;

@@ -248,7 +248,16 @@ __device__ __forceinline__ TileLines<SETS> tile_lines(int64_t tile, int c, const
             // row of output column `line` is its digit reversal within its
             // signal (row_mul = N / L columns per signal of a batch)
             const int64_t cols = sp.row_mul;
-            a.blk[st] = (line & ~(cols - 1)) | int64_t(digit_reverse(uint64_t(line & (cols - 1)), sp.rev));
+            if (sp.ilv > 1) {
+                // interleaved output: line l of a group of ilv signals is
+                // output column l, i.e. column l / ilv of signal l mod ilv
+                const int64_t gl = cols * sp.ilv;
+                const int64_t g = line / gl, l2 = line - g * gl;
+                const int64_t cc = l2 / sp.ilv, b = l2 - cc * sp.ilv;
+                a.blk[st] = (g * sp.ilv + b) * cols + int64_t(digit_reverse(uint64_t(cc), sp.rev));
+            } else {
+                a.blk[st] = (line & ~(cols - 1)) | int64_t(digit_reverse(uint64_t(line & (cols - 1)), sp.rev));
+            }
             a.off[st] = 0;
             a.base[st] = a.blk[st] * L;
         } else {
@@ -319,13 +328,19 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
         const int t2 = tid / LINES;
         const int64_t cols = sp.row_mul;
         const int64_t line = a.tile * LINES + c2;
-        const int64_t col = (line & ~(cols - 1)) * L + (line & (cols - 1));  // signal * N + column
+        int64_t col = (line & ~(cols - 1)) * L + (line & (cols - 1));  // signal * N + column
+        int64_t ostride = cols;
+        if (sp.ilv > 1) {  // group * (ilv N) + column l of the group, columns ilv * cols apart
+            ostride = cols * sp.ilv;
+            const int64_t g = line / ostride;
+            col = g * ostride * L + (line - g * ostride);
+        }
         const V *col_lds = lds + c2 * PADDED;
         V w[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) w[i] = col_lds[lds_pad(t2 + P * i)];
         finish_outputs<V, E>(w, sp);
-        store_points<V, E>(dst + col + cols * int64_t(t2), cols * int64_t(P), w, sp.nt_store);
+        store_points<V, E>(dst + col + ostride * int64_t(t2), ostride * int64_t(P), w, sp.nt_store);
     } else if constexpr (LAYOUT != LAYOUT_COL2ROW) {
 #pragma unroll
         for (int st = 0; st < SETS; ++st) {

@@ -8,6 +8,9 @@
 //   radix-M pass  work[k1 * 2^s + n2] = W_N^{n2 k1} * DFT_M(x[. * 2^s + n2])[k1]
 //   M batched 2^s-point transforms of the rows of work (the power-of-two passes)
 //   reorder       out[k2 * M + k1] = scale * work[k1 * 2^s + k2]
+// When the rows take two or more passes, the reorder is the last of them (a
+// row-to-column pass that writes the rows interleaved); the reorder kernel
+// here serves rows of a single pass.
 // The paper's EFFT takes the same size class (Section 2.2, Section 4), with
 // the M-point transforms left to MKL; here they are direct sums in FP64.
 //

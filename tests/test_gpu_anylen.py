@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from paper_1409_5757_amd import api
+from paper_1409_5757_amd import _lib, api
 from tests.gpu_util import NP, TOL, host_input, oracle_bins_from_device, rel_l2, run_library, sample_bins
 
 pytestmark = pytest.mark.gpu
@@ -133,3 +133,45 @@ def test_small_odd_factor_batch_and_placement_bitwise(dtype):
         assert torch.equal(w, y)
         z = api.ifft(y)
         assert rel_l2(z.cpu().numpy(), x.cpu().numpy()) < (1e-13 if dtype == torch.complex128 else 3e-6)
+
+
+FUSED = [(3, 13), (5, 13), (7, 13), (3, 14)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_small_odd_factor_fused_rows_every_bin(dtype):
+    """Rows of two or more digits end with a pass that writes them interleaved
+    straight into the output (no reorder pass): every bin against the direct
+    sum, both directions, in place and out of place."""
+    for i, (m, s) in enumerate(FUSED):
+        n = m << s
+        digits, _ = _lib.schedule(1 << s, 2 if dtype == torch.complex128 else 1, True)
+        p = api.Plan(n, dtype, -1, False, device=torch.device("cuda", 0))
+        assert len(digits) >= 2 and p.passes == 1 + len(digits), (m, s, digits, p.passes)
+        p.close()
+        x = host_input("uniform", 9000 + n, n, dtype)
+        direction = -1 if i % 2 == 0 else 1
+        inplace = i % 2 == 1
+        got, after = run_library(x, dtype, direction, inplace)
+        err = rel_l2(got, oracle.dft(x, direction))
+        print(f"n={m}*2^{s} {dtype} dir={direction} inplace={inplace}: rel_l2={err:.2e}", flush=True)
+        assert err <= TOL[dtype], (m, s, err)
+        if after is not None:
+            np.testing.assert_array_equal(after, x)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_small_odd_factor_fused_rows_batch_scale_placement(dtype):
+    n = 5 << 13
+    x = torch.from_numpy(np.stack([host_input("normal", 300 + r, n, dtype) for r in range(3)])).cuda()
+    y = api.fft(x)
+    for r in range(3):
+        assert torch.equal(api.fft(x[r].contiguous()), y[r])
+    w = x.clone()
+    api.fft(w, inplace=True)
+    assert torch.equal(w, y)
+    # the inverse scales by 1/N (not a power of two) in the interleaving pass
+    z = api.ifft(y)
+    assert rel_l2(z.cpu().numpy(), x.cpu().numpy()) < (1e-13 if dtype == torch.complex128 else 3e-6)
+    ref = oracle.dft(x[1].cpu().numpy(), +1) / n
+    assert rel_l2(api.ifft(x[1].contiguous()).cpu().numpy(), ref) <= TOL[dtype]
