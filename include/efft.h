@@ -105,8 +105,11 @@ enum {
  * the chirp (N FP64 complex values), the transformed convolution kernel and
  * a work array (M elements of dtype each; see efft_plan_bytes), so at most
  * one execution of it may be in flight at a time.  Each execution runs, per
- * signal: a pre-multiply pass, an M-point forward transform, a pointwise
- * product, an M-point backward transform and a post-multiply pass.
+ * signal: a pre-multiply, an M-point forward transform, a pointwise product,
+ * an M-point backward transform and a post-multiply pass.  When the M-point
+ * transforms run out of place (the device has room for a second work array),
+ * the pre-multiply and the pointwise product are applied by the first pass
+ * of each transform as it loads, so they add no pass of their own.
  */
 efft_plan_t *efft_plan(int64_t n, int dtype, int dir, int inplace);
 

@@ -172,6 +172,10 @@ struct efft_plan_s {
     efft_plan_s *inner2;
     double2 *chirp;
     void *vhat, *work, *work2;  // work2: second work array of out-of-place inner plans
+    // out-of-place inner plans: their passes with the premultiplication by the
+    // chirp (forward) and the product with V (backward) done by the first
+    // pass as it loads, so neither takes a pass of its own
+    std::vector<Pass> chirp_fwd, chirp_bwd;
     // N = M * 2^s with a small odd M (KIND_MIXED): tables (W_M, lo, hi of W_N)
     // in `tables`, rows of 2^s points transformed by `inner` (batch M), work
     int m_odd, h_mixed;
@@ -420,8 +424,8 @@ int run_passes(const std::vector<Pass> &passes, int64_t batch, int eb, const voi
 int total_passes(const efft_plan_s *p)
 {
     if (p->kind == KIND_C2C) return int(p->passes.size());
-    if (p->kind == KIND_CHIRP)  // premul, M-point forward, product, M-point backward, postmul
-        return int(p->inner->passes.size()) + int(p->inner2->passes.size()) + 3;
+    if (p->kind == KIND_CHIRP)  // (premul,) M-point forward, (product,) M-point backward, postmul
+        return int(p->inner->passes.size()) + int(p->inner2->passes.size()) + (p->chirp_fwd.empty() ? 3 : 1);
     if (p->kind == KIND_MIXED)  // radix-M pass, the rows' passes (and a reorder)
         return p->mixed_passes.empty() ? int(p->inner->passes.size()) + 2 : int(p->mixed_passes.size()) + 1;
     return int(p->inner->passes.size()) + 1;
@@ -456,7 +460,9 @@ int run_mixed(const efft_plan_s *p, const void *in, void *out, hipStream_t strea
 }
 
 // Chirp plan: per signal, w = (x a) zero-padded; w = DFT_M(w); w *= V;
-// w = DFT_M^-(w) (the 1/M is in V); out = scale * a * w[0 .. N).
+// w = DFT_M^-(w) (the 1/M is in V); out = scale * a * w[0 .. N).  With
+// out-of-place M-point plans the first two products happen in the first
+// pass of each transform, as it loads.
 int run_chirp(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events, int nevents)
 {
     const int np = total_passes(p);
@@ -468,6 +474,19 @@ int run_chirp(const efft_plan_s *p, const void *in, void *out, hipStream_t strea
     for (int64_t b = 0; b < p->batch; ++b) {
         const char *x = static_cast<const char *>(in) + b * p->n * p->eb;
         char *y = static_cast<char *>(out) + b * p->n * p->eb;
+        if (!p->chirp_fwd.empty()) {
+            // x -> work2 (premultiplied and zero-padded as loaded), work2 ->
+            // work (times V as loaded), postmul work -> y
+            int r = run_passes(p->chirp_fwd, 1, p->eb, x, p->work2, nullptr, stream, events, events ? nf + 1 : 0);
+            if (r != EFFT_OK) return r;
+            r = run_passes(p->chirp_bwd, 1, p->eb, p->work2, p->work, nullptr, stream, events ? events + nf : nullptr,
+                           events ? nb + 1 : 0);
+            if (r != EFFT_OK) return r;
+            if (launch_postmul(p->eb, p->work, y, p->chirp, p->n, p->scale, stream) != hipSuccess ||
+                !rec(np))
+                return EFFT_ERR_HIP;
+            continue;
+        }
         if (!rec(0) || launch_premul(p->eb, x, p->work, p->chirp, p->n, p->m_pad, stream) != hipSuccess)
             return EFFT_ERR_HIP;
         // out-of-place inner plans (when the device has room): work -> work2 -> work
@@ -820,6 +839,16 @@ efft_plan_s *create_chirp(int64_t n, int64_t batch, int dtype, int dir, int inpl
         return nullptr;
     }
     p->table_bytes = int64_t(n) * int64_t(sizeof(double2)) + (oop ? 3 : 2) * m * int64_t(eb);
+    if (oop && p->inner->passes.front().layout == LAYOUT_COL2ROW &&
+        p->inner2->passes.front().layout == LAYOUT_COL2ROW) {
+        p->chirp_fwd = p->inner->passes;
+        p->chirp_fwd.front().sp.pmode = PRE_CHIRP;
+        p->chirp_fwd.front().sp.pre = p->chirp;
+        p->chirp_fwd.front().sp.n_valid = n;
+        p->chirp_bwd = p->inner2->passes;
+        p->chirp_bwd.front().sp.pmode = PRE_MUL;
+        p->chirp_bwd.front().sp.pre = p->vhat;
+    }
     // V = DFT_M(v) / M, formed in the work array and transformed into vhat
     // (in place when the inner plans are)
     void *vsrc = oop ? p->work : p->vhat;

@@ -26,6 +26,15 @@ enum TwMode : int {
     TW_REVBLOCK = 2  // W_N^(rev(b) * k * scale), rev = digit reversal of b
 };
 
+// What a LAYOUT_COL2ROW pass applies to each point it loads (point n of the
+// signal): the factors of a pointwise product, or the chirp of a length that
+// is not a power of two, with zero padding beyond the signal.
+enum PreMode : int {
+    PRE_NONE = 0,
+    PRE_MUL = 1,   // src[n] * pre[n] (pre in the storage type)
+    PRE_CHIRP = 2  // n < n_valid: src[n] * pre[n] in FP64 (pre: double2), rounded once; else 0
+};
+
 // Order in which workgroups visit the tiles of a pass (see order_tiles).
 enum TileOrder : int { TILE_LINEAR = 0, TILE_XCD = 1, TILE_XCD_SCATTER = 2 };
 
@@ -59,6 +68,9 @@ struct StageParams {
     uint64_t tw_scale;   // see TwMode
     int64_t row_mul;     // LAYOUT_COL2ROW: line o's row starts at row_mul * rev(o);
                          // LAYOUT_ROW2COL: column stride of the output
+    const void *pre;     // LAYOUT_COL2ROW: factors applied on load (see PreMode)
+    int64_t n_valid;     // PRE_CHIRP: points of the source signal
+    int pmode;           // PreMode
     int64_t ilv;         // LAYOUT_ROW2COL: signals interleaved in the output (1: none).
                          // With ilv = M, bin k of signal b of each group of M signals
                          // lands at k * M + b of that group's M * N outputs

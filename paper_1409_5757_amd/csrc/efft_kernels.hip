@@ -288,6 +288,42 @@ __device__ __forceinline__ void load_tile(V (&v)[SETS][E], const TileLines<SETS>
     }
 }
 
+// load_tile with the factors of a PreMode (transposing first passes only):
+// the same products, in the same precision, as a separate pointwise pass.
+template <typename V, int E, int P, int SETS>
+__device__ __forceinline__ void load_tile_pre(V (&v)[SETS][E], const TileLines<SETS> &a, const V *src, int t,
+                                              const StageParams &sp)
+{
+    using T = decltype(V{}.x);
+    if (sp.pmode == PRE_MUL) {
+        const V *f = static_cast<const V *>(sp.pre);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+#pragma unroll
+            for (int st = 0; st < SETS; ++st) {
+                const int64_t n = a.base[st] + sp.s * int64_t(t + P * i);
+                v[st][i] = cmul(sp.nt_load ? load_nt(src + n) : src[n], f[n]);
+            }
+        }
+    } else {
+        const double2 *c = static_cast<const double2 *>(sp.pre);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+#pragma unroll
+            for (int st = 0; st < SETS; ++st) {
+                const int64_t n = a.base[st] + sp.s * int64_t(t + P * i);
+                V r{T(0), T(0)};
+                if (n < sp.n_valid) {
+                    const V x = sp.nt_load ? load_nt(src + n) : src[n];
+                    const double2 pr = cmul(double2{double(x.x), double(x.y)}, c[n]);
+                    r = V{T(pr.x), T(pr.y)};
+                }
+                v[st][i] = r;
+            }
+        }
+    }
+}
+
 // Stores of E points of a thread, point i at p + stride * i.
 template <typename V, int E>
 __device__ __forceinline__ void store_points(V *p, int64_t stride, const V *w, int nt)
@@ -425,14 +461,23 @@ __global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()))
 
     V v[SETS][E];
     TileLines<SETS> a = tile_lines<L, LINES, SETS, LAYOUT>(order_tiles(vbid(0), sp.ntiles, sp.order), c, sp);
-    load_tile<V, E, P, SETS>(v, a, src, t, sp.s, sp.nt_load);
+    auto load = [&](V(&dst_v)[SETS][E], const TileLines<SETS> &at) {
+        if constexpr (LAYOUT == LAYOUT_COL2ROW) {
+            if (sp.pmode != PRE_NONE) {
+                load_tile_pre<V, E, P, SETS>(dst_v, at, src, t, sp);
+                return;
+            }
+        }
+        load_tile<V, E, P, SETS>(dst_v, at, src, t, sp.s, sp.nt_load);
+    };
+    load(v, a);
 #pragma unroll
     for (int it = 0; it < PIPE; ++it) {
         V vn[SETS][E];
         TileLines<SETS> an;
         if (it + 1 < PIPE) {
             an = tile_lines<L, LINES, SETS, LAYOUT>(order_tiles(vbid(it + 1), sp.ntiles, sp.order), c, sp);
-            load_tile<V, E, P, SETS>(vn, an, src, t, sp.s, sp.nt_load);
+            load(vn, an);
         }
         if (it > 0) __syncthreads();  // the previous tile has finished with LDS
         process_tile<V, LOGL, LINES, SETS, LAYOUT, EP>(v, a, lds, dst, c, t, tid, sp);
