@@ -1,0 +1,79 @@
+"""Every size between the every-bin parity sizes (up to 2^24) and the full
+workloads: 2^25 .. 2^29, 2^31 and 2^33, whose decompositions use digit
+shapes the other tests do not all reach.  On every bin, the closed-form
+spectrum of a sum of 8 integer-frequency tones (N e^{i phi} at each
+frequency, zero elsewhere); on uniform inputs, sampled bins against the
+oracle's direct sum of Eq. "eqf" (error per bin relative to the RMS of the
+spectrum, which is ||x||_2 by Parseval).  Both precisions, in place and out
+of place where the device holds the arrays."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1409_5757_amd import api, inputs
+from tests.gpu_util import TOL, oracle_bins_from_device, sample_bins
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+DEV = torch.device("cuda", 0)
+DTYPES = [torch.complex128, torch.complex64]
+SIZES = [25, 26, 27, 28, 29, 31, 33]
+CHUNK = 1 << 26
+
+
+def _fits(nbytes: int) -> bool:
+    free, _ = torch.cuda.mem_get_info(DEV)
+    return nbytes + (4 << 30) <= free
+
+
+def _transform(x: torch.Tensor, inplace: bool) -> torch.Tensor:
+    p = api.get_plan(x.shape[0], x.dtype, -1, inplace, 1.0, DEV)
+    if inplace:
+        return p.execute(x)
+    return p.execute(x, out=torch.empty_like(x))
+
+
+@pytest.mark.parametrize("q", SIZES)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_tones_every_bin(q, dtype):
+    n = 1 << q
+    eb = 16 if dtype == torch.complex128 else 8
+    tol = 1e-12 if dtype == torch.complex128 else 1e-5
+    f, v = inputs.tone_spectrum_peaks(q, n)
+    fi = torch.from_numpy(f).to(DEV)
+    ran = 0
+    for inplace in (True, False):
+        if not _fits(n * eb * (1 if inplace else 2)):
+            continue
+        x = torch.empty(n, dtype=dtype, device=DEV)
+        inputs.fill_tones_torch(x, seed=q)
+        y = _transform(x, inplace)
+        torch.cuda.synchronize()
+        perr = float(np.max(np.abs(y[fi].cpu().numpy() - v))) / n
+        y[fi] = 0
+        rest = max(float(y[i:i + CHUNK].abs().max()) for i in range(0, n, CHUNK)) / n
+        print(f"2^{q} {dtype} inplace={inplace}: tone peak err/N={perr:.2e} off-peak max/N={rest:.2e}",
+              flush=True)
+        assert perr < tol and rest < tol, (perr, rest)
+        ran += 1
+        del x, y
+        torch.cuda.empty_cache()
+    assert ran >= 1
+
+
+@pytest.mark.parametrize("q", SIZES[:5])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_uniform_sampled_bins(q, dtype):
+    n = 1 << q
+    x = torch.empty(n, dtype=dtype, device=DEV)
+    inputs.fill_uniform_torch(x, seed=q)
+    bins = sample_bins(n, 12, seed=q)
+    ref = oracle_bins_from_device(x, bins)
+    rms = float(torch.linalg.vector_norm(x.to(torch.complex128)))
+    for inplace in (False, True):
+        y = _transform(x if not inplace else x.clone(), inplace)
+        err = float(np.max(np.abs(y[torch.from_numpy(bins).to(DEV)].cpu().numpy() - ref))) / rms
+        print(f"2^{q} {dtype} inplace={inplace}: max sampled-bin error / rms = {err:.2e}", flush=True)
+        assert err <= TOL[dtype]
+        del y
+    torch.cuda.empty_cache()
