@@ -38,20 +38,21 @@ __global__ void __launch_bounds__(256) r2c_post_kernel(typename vec2<T>::type *z
             continue;
         }
         const int64_t j = h - k;
-        const V a = z[k];
-        const V b = z[j];
+        const V a = load_nt(z + k);
+        const V b = load_nt(z + j);
         // E_k = (a + conj b)/2, O_k = (a - conj b)/(2i) = (-i/2)(a - conj b)
         const V e = V{half * (a.x + b.x), half * (a.y - b.y)};
         const V d = V{half * (a.x - b.x), half * (a.y + b.y)};  // (a - conj b)/2
         const V o = V{d.y, -d.x};                                // times -i
         const V wk = round_tw<V>(tw_lookup(tt, uint64_t(k)));
         const V fk = cadd(e, cmul(wk, o));
-        z[k] = V{fk.x * f, fk.y * f};
+        store_nt(z + k, V{fk.x * f, fk.y * f});
         if (j != k) {
             // E_j = conj E_k, O_j = conj O_k (Hermitian), F_j = E_j + W_N^j O_j
-            const V wj = round_tw<V>(tw_lookup(tt, uint64_t(j)));
+            // with W_N^j = W_N^(N/2 - k) = -conj(W_N^k)
+            const V wj = V{-wk.x, wk.y};
             const V fj = cadd(cconj(e), cmul(wj, cconj(o)));
-            z[j] = V{fj.x * f, fj.y * f};
+            store_nt(z + j, V{fj.x * f, fj.y * f});
         }
     }
 }
@@ -65,8 +66,8 @@ __global__ void __launch_bounds__(256) c2r_pre_kernel(const typename vec2<T>::ty
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k <= h / 2; k += stride) {
         const int64_t j = h - k;
-        V a = f[k];
-        V b = f[j];
+        V a = load_nt(f + k);
+        V b = load_nt(f + j);
         if (k == 0) {  // F_0 and F_{N/2} of a Hermitian spectrum are real
             a.y = T(0);
             b.y = T(0);
@@ -76,13 +77,13 @@ __global__ void __launch_bounds__(256) c2r_pre_kernel(const typename vec2<T>::ty
         const V d = V{a.x - b.x, a.y + b.y};
         const V wk = cconj(round_tw<V>(tw_lookup(tt, uint64_t(k))));
         const V t = cmul(wk, d);
-        z[k] = V{s.x - t.y, s.y + t.x};
+        store_nt(z + k, V{s.x - t.y, s.y + t.x});
         if (k != 0 && j != k) {
             const V s2 = cconj(s);        // b + conj a
             const V d2 = V{-d.x, d.y};    // b - conj a = -conj(d)
-            const V wj = cconj(round_tw<V>(tw_lookup(tt, uint64_t(j))));
+            const V wj = V{-wk.x, wk.y};  // conj(W_N^(N/2 - k)) = -W_N^k, and wk = conj(W_N^k)
             const V t2 = cmul(wj, d2);
-            z[j] = V{s2.x - t2.y, s2.y + t2.x};
+            store_nt(z + j, V{s2.x - t2.y, s2.y + t2.x});
         }
     }
 }
