@@ -97,10 +97,10 @@ __global__ void __launch_bounds__(BT) postmul_kernel(const V *w, V *out, const d
     using T = decltype(V{}.x);
     const int64_t stride = int64_t(gridDim.x) * BT;
     for (int64_t j = int64_t(blockIdx.x) * BT + threadIdx.x; j < n; j += stride) {
-        const V v = w[j];
-        const double2 c = a[j];
+        const V v = load_nt(w + j);
+        const double2 c = load_nt(a + j);
         const double2 p = cmul(double2{double(v.x), double(v.y)}, double2{c.x * scale, c.y * scale});
-        out[j] = V{T(p.x), T(p.y)};
+        store_nt(out + j, V{T(p.x), T(p.y)});
     }
 }
 

@@ -65,7 +65,8 @@ struct MixedParams {
 
 // One column n2 of one signal per thread: M loads at stride 2^s (adjacent
 // threads read adjacent addresses), the M-point DFT in FP64, the twiddle
-// W_N^{n2 k1}, M stores at stride 2^s.
+// W_N^{n2 k1}, M stores at stride 2^s; data loads and stores stream past the
+// caches (non-temporal), which keep the twiddle tables.
 template <typename V, int M>
 __global__ void __launch_bounds__(BT) radix_m_kernel(MixedParams p)
 {
@@ -85,7 +86,7 @@ __global__ void __launch_bounds__(BT) radix_m_kernel(MixedParams p)
         double2 xv[M];
 #pragma unroll
         for (int n1 = 0; n1 < M; ++n1) {
-            const V v = x[base + n1 * p.cols];
+            const V v = load_nt(x + base + n1 * p.cols);
             xv[n1] = double2{double(v.x), double(v.y)};
         }
 #pragma unroll
@@ -102,7 +103,7 @@ __global__ void __launch_bounds__(BT) radix_m_kernel(MixedParams p)
             double2 tw = cmul(hv, lv);
             tw.y *= sg;
             const double2 r = cmul(acc, tw);
-            w[base + k1 * p.cols] = V{T(r.x), T(r.y)};
+            store_nt(w + base + k1 * p.cols, V{T(r.x), T(r.y)});
         }
     }
 }
