@@ -302,7 +302,7 @@ __device__ __forceinline__ void load_tile_pre(V (&v)[SETS][E], const TileLines<S
 #pragma unroll
             for (int st = 0; st < SETS; ++st) {
                 const int64_t n = a.base[st] + sp.s * int64_t(t + P * i);
-                v[st][i] = cmul(sp.nt_load ? load_nt(src + n) : src[n], f[n]);
+                v[st][i] = sp.nt_load ? cmul(load_nt(src + n), load_nt(f + n)) : cmul(src[n], f[n]);
             }
         }
     } else {
@@ -315,7 +315,8 @@ __device__ __forceinline__ void load_tile_pre(V (&v)[SETS][E], const TileLines<S
                 V r{T(0), T(0)};
                 if (n < sp.n_valid) {
                     const V x = sp.nt_load ? load_nt(src + n) : src[n];
-                    const double2 pr = cmul(double2{double(x.x), double(x.y)}, c[n]);
+                    const double2 cn = sp.nt_load ? load_nt(c + n) : c[n];
+                    const double2 pr = cmul(double2{double(x.x), double(x.y)}, cn);
                     r = V{T(pr.x), T(pr.y)};
                 }
                 v[st][i] = r;
