@@ -279,6 +279,23 @@ int efft_plan_passes(const efft_plan_t *plan);
 int efft_schedule(int64_t n, int dtype, int inplace, int *log2_radix, int max_digits,
                   int *passes);
 
+/*
+ * Memory-bandwidth reference: copies `bytes` bytes from src to dst, enqueued
+ * on `stream` (a hipStream_t; NULL is the default stream).  The paper sets
+ * EFFT beside the STREAM benchmark (Section 5.4, Fig. "fig:parallel-perf");
+ * this is the GPU counterpart, a streaming copy with the access style of the
+ * transform's passes (16-byte accesses with the non-temporal hint), which the
+ * benchmark reports as the achievable copy bandwidth.  dst and src are device
+ * pointers, both 16-byte aligned (else EFFT_ERR_ALIGN), non-NULL (else
+ * EFFT_ERR_NULLPTR), with ranges that do not overlap (else
+ * EFFT_ERR_OVERLAP) unless dst == src, which rewrites the range in place
+ * (the access pattern of an in-place pass); bytes must be a non-negative
+ * multiple of 16 (else
+ * EFFT_ERR_ARG), and 0 enqueues nothing.  EFFT_ERR_HIP if the launch fails.
+ * The arguments are checked on the host before anything is enqueued.
+ */
+int efft_stream_copy(void *dst, const void *src, int64_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,8 @@ def _bind(lib):
     lib.efft_plan_passes.restype = ci
     lib.efft_schedule.argtypes = [i64, ci, ci, ctypes.POINTER(ci), ci, ctypes.POINTER(ci)]
     lib.efft_schedule.restype = ci
+    lib.efft_stream_copy.argtypes = [vp, vp, i64, vp]
+    lib.efft_stream_copy.restype = ci
     return lib
 
 

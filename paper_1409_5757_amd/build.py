@@ -13,7 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libefft.so")
-SOURCES = ["efft_api.hip", "efft_kernels.hip", "efft_real.hip", "efft_bluestein.hip", "efft_mixed.hip"]
+SOURCES = ["efft_api.hip", "efft_kernels.hip", "efft_real.hip", "efft_bluestein.hip", "efft_mixed.hip",
+           "efft_stream.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code: the compiler

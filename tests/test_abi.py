@@ -73,6 +73,22 @@ def test_null_and_dead_handles(lib):
     assert lib.efft_destroy(ctypes.addressof(fake)) == -10
 
 
+def test_stream_copy_rejects_invalid_arguments(lib):
+    """Argument checks happen on the host before anything is enqueued (the
+    addresses below are never dereferenced)."""
+    a, b = 1 << 20, 1 << 24  # 16-byte aligned, far apart
+    assert lib.efft_stream_copy(None, b, 64, None) == -4
+    assert lib.efft_stream_copy(a, None, 64, None) == -4
+    assert lib.efft_stream_copy(a + 8, b, 64, None) == -5
+    assert lib.efft_stream_copy(a, b + 4, 64, None) == -5
+    assert lib.efft_stream_copy(a, b, 24, None) == -11
+    assert lib.efft_stream_copy(a, b, -16, None) == -11
+    assert lib.efft_stream_copy(a, a + 32, 64, None) == -7
+    assert lib.efft_stream_copy(a + 32, a, 64, None) == -7
+    assert lib.efft_stream_copy(a, b, 0, None) == 0  # nothing to enqueue
+    assert lib.efft_stream_copy(a, a, 0, None) == 0  # in place, nothing to enqueue
+
+
 def _sched(n, dtype, inplace):
     return _lib.schedule(n, dtype, inplace)
 

@@ -93,3 +93,22 @@ def test_batched_error_paths():
     with pytest.raises(ValueError):
         p.execute(torch.zeros(2, 1 << 14, dtype=torch.complex128, device=dev))  # 2 rows, batch 3
     torch.cuda.synchronize()
+
+
+def test_stream_copy():
+    """The bandwidth reference copies exactly, on the caller's stream, for
+    sizes that are and are not multiples of its 16 KiB block."""
+    lib = _lib.load()
+    dev = torch.device("cuda", 0)
+    s = torch.cuda.Stream(dev)
+    for nbytes in (16, 4096, 16384 + 48, (1 << 24) + 16 * 7):
+        a = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device=dev)
+        b = torch.zeros(nbytes + 64, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            rc = lib.efft_stream_copy(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()), nbytes,
+                                      ctypes.c_void_p(s.cuda_stream))
+        assert rc == 0
+        s.synchronize()
+        assert torch.equal(b[:nbytes], a)
+        assert int(b[nbytes:].sum()) == 0  # nothing written past the end
