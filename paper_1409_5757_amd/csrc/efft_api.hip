@@ -547,6 +547,7 @@ int run_passes(const std::vector<Pass> &passes, int64_t batch, int eb, const voi
         } else {
             ps.sp.src = bufs[ps.src];
             ps.sp.dst = bufs[ps.dst];
+            ps.sp.scatter = scatter_stride(ps.layout, ps.lines, ps.sets, eb);
             e = launch_stage(eb, ps.layout, ps.logl, ps.lines, ps.sets, ps.sp, stream);
         }
         if (e != hipSuccess) return EFFT_ERR_HIP;
@@ -842,10 +843,12 @@ efft_plan_s *create_chirp(int64_t n, int64_t batch, int dtype, int dir, int inpl
     if (oop && p->inner->passes.front().layout == LAYOUT_COL2ROW &&
         p->inner2->passes.front().layout == LAYOUT_COL2ROW) {
         p->chirp_fwd = p->inner->passes;
+        p->chirp_fwd.front().layout = LAYOUT_COL2ROW_PRE;
         p->chirp_fwd.front().sp.pmode = PRE_CHIRP;
         p->chirp_fwd.front().sp.pre = p->chirp;
         p->chirp_fwd.front().sp.n_valid = n;
         p->chirp_bwd = p->inner2->passes;
+        p->chirp_bwd.front().layout = LAYOUT_COL2ROW_PRE;
         p->chirp_bwd.front().sp.pmode = PRE_MUL;
         p->chirp_bwd.front().sp.pre = p->vhat;
     }

@@ -14,9 +14,12 @@ enum Layout : int {
                         // every row of its tile is one contiguous W-element run
     LAYOUT_COL2ROW = 2, // strided lines read as LAYOUT_COL, each written back
                         // as a contiguous row at a digit-reversed row index
-    LAYOUT_ROW2COL = 3  // contiguous rows read from a scratch array, each
+    LAYOUT_ROW2COL = 3, // contiguous rows read from a scratch array, each
                         // written as a strided column of the output, in
                         // natural order (the last pass of a scratch plan)
+    LAYOUT_COL2ROW_PRE = 4  // LAYOUT_COL2ROW whose loads apply the factors of
+                            // sp.pmode (separate kernels, so the plain
+                            // transposing pass keeps its own code)
 };
 
 // Twiddle applied to output k of line (block b, offset o) of a pass.
@@ -26,7 +29,7 @@ enum TwMode : int {
     TW_REVBLOCK = 2  // W_N^(rev(b) * k * scale), rev = digit reversal of b
 };
 
-// What a LAYOUT_COL2ROW pass applies to each point it loads (point n of the
+// What a LAYOUT_COL2ROW_PRE pass applies to each point it loads (point n of the
 // signal): the factors of a pointwise product, or the chirp of a length that
 // is not a power of two, with zero padding beyond the signal.
 enum PreMode : int {
@@ -68,7 +71,7 @@ struct StageParams {
     uint64_t tw_scale;   // see TwMode
     int64_t row_mul;     // LAYOUT_COL2ROW: line o's row starts at row_mul * rev(o);
                          // LAYOUT_ROW2COL: column stride of the output
-    const void *pre;     // LAYOUT_COL2ROW: factors applied on load (see PreMode)
+    const void *pre;     // LAYOUT_COL2ROW_PRE: factors applied on load (see PreMode)
     int64_t n_valid;     // PRE_CHIRP: points of the source signal
     int pmode;           // PreMode
     int64_t ilv;         // LAYOUT_ROW2COL: signals interleaved in the output (1: none).
@@ -82,6 +85,7 @@ struct StageParams {
     int conj;            // 1: backward direction (conjugate on load and store)
     int apply_scale;
     int order;           // TileOrder
+    int64_t scatter;     // TILE_XCD_SCATTER: odd stride, in tiles, of each XCD's walk
     int nt_load;         // 1: data loads carry the non-temporal (streaming) hint
     int nt_store;        // 1: data stores carry it
 };
@@ -199,6 +203,17 @@ constexpr int64_t WIDE_TILE_STRIDE = int64_t(1) << 17;
 // Tile order of a strided pass (measured: the scattered order is 5-10%
 // faster from a 2^17-element stride up, the plain XCD order below it)
 inline int col_order(int64_t stride) { return stride >= WIDE_TILE_STRIDE ? TILE_XCD_SCATTER : TILE_XCD; }
+
+// Stride of the scattered walk.  Measured on gfx950 over 7 .. 4099: strided
+// passes whose tile rows are 256-byte runs (complex128 lines of 1024 points
+// in two sets of 8, complex64 lines of 512 points 32 wide) run best at 127 -
+// 129 tiles (2^30 complex128 in place, first pass 8.03 -> 7.78 ms; 2^34
+// complex64, 81.3 -> 78.5 ms), while the transposing first pass of 2^32
+// complex64 (512-byte rows) lost 17% there and keeps 1031.
+inline int64_t scatter_stride(int layout, int lines, int sets, int dtype_bytes)
+{
+    return (layout == LAYOUT_COL && lines * sets * dtype_bytes == 256) ? 129 : 1031;
+}
 
 // Lines per workgroup for complex64 lines of 1024 points at a small stride:
 // the 16-line tile fills the LDS, one workgroup per CU; an 8-line tile lets

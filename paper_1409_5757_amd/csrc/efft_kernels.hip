@@ -215,8 +215,9 @@ __device__ __forceinline__ void finish_outputs(V *v, const StageParams &sp)
 // so neighbouring tiles (adjacent row segments) are in flight on one XCD at
 // the same time; TILE_XCD_SCATTER additionally walks each XCD's run with an
 // odd multiplicative stride, which spreads concurrent tiles of a pass whose
-// lines are far apart in memory over more DRAM channels.
-__device__ __forceinline__ int64_t order_tiles(int64_t bid, int64_t ntiles, int mode)
+// lines are far apart in memory over more DRAM channels; `mul` is that
+// stride in tiles (odd; chosen per pass by scatter_stride).
+__device__ __forceinline__ int64_t order_tiles(int64_t bid, int64_t ntiles, int mode, int64_t mul = 1)
 {
     // the multiplicative walk is a permutation only for a power-of-two count
     // (a batch of 3 signals, say, has 3 * 2^k tiles): use the plain XCD order
@@ -224,7 +225,7 @@ __device__ __forceinline__ int64_t order_tiles(int64_t bid, int64_t ntiles, int 
     if (mode == TILE_XCD && (ntiles & 7) == 0) return (bid & 7) * (ntiles >> 3) + (bid >> 3);
     if (mode == TILE_XCD_SCATTER && (ntiles & 63) == 0) {
         const int64_t c = ntiles >> 3, k = bid >> 3;  // c is a power of two
-        return (bid & 7) * c + ((k * 1031) & (c - 1));
+        return (bid & 7) * c + ((k * mul) & (c - 1));
     }
     return bid;
 }
@@ -378,7 +379,7 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
         for (int i = 0; i < E; ++i) w[i] = col_lds[lds_pad(t2 + P * i)];
         finish_outputs<V, E>(w, sp);
         store_points<V, E>(dst + col + ostride * int64_t(t2), ostride * int64_t(P), w, sp.nt_store);
-    } else if constexpr (LAYOUT != LAYOUT_COL2ROW) {
+    } else if constexpr (LAYOUT != LAYOUT_COL2ROW && LAYOUT != LAYOUT_COL2ROW_PRE) {
 #pragma unroll
         for (int st = 0; st < SETS; ++st) {
             if (st > 0) __syncthreads();  // the previous set has finished with LDS
@@ -434,8 +435,10 @@ __global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()))
     constexpr int P = LineGeom<L, EP>::P;
     constexpr int PADDED = LineGeom<L, EP>::PADDED;
     constexpr bool NEED_LDS =
-        (Radices<LOGL>::NSTEPS > 1) || (LAYOUT == LAYOUT_COL2ROW) || (LAYOUT == LAYOUT_ROW2COL);
-    static_assert(LAYOUT != LAYOUT_COL2ROW || SETS == 1, "one line set for row writes");
+        (Radices<LOGL>::NSTEPS > 1) || (LAYOUT == LAYOUT_COL2ROW) || (LAYOUT == LAYOUT_COL2ROW_PRE) ||
+        (LAYOUT == LAYOUT_ROW2COL);
+    static_assert((LAYOUT != LAYOUT_COL2ROW && LAYOUT != LAYOUT_COL2ROW_PRE) || SETS == 1,
+                  "one line set for row writes");
     static_assert(LAYOUT != LAYOUT_ROW2COL || SETS == 1, "one line set for column writes");
     __shared__ V lds[NEED_LDS ? LINES * PADDED : PADDED];
 
@@ -461,15 +464,13 @@ __global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()))
     };
 
     V v[SETS][E];
-    TileLines<SETS> a = tile_lines<L, LINES, SETS, LAYOUT>(order_tiles(vbid(0), sp.ntiles, sp.order), c, sp);
+    TileLines<SETS> a =
+        tile_lines<L, LINES, SETS, LAYOUT>(order_tiles(vbid(0), sp.ntiles, sp.order, sp.scatter), c, sp);
     auto load = [&](V(&dst_v)[SETS][E], const TileLines<SETS> &at) {
-        if constexpr (LAYOUT == LAYOUT_COL2ROW) {
-            if (sp.pmode != PRE_NONE) {
-                load_tile_pre<V, E, P, SETS>(dst_v, at, src, t, sp);
-                return;
-            }
-        }
-        load_tile<V, E, P, SETS>(dst_v, at, src, t, sp.s, sp.nt_load);
+        if constexpr (LAYOUT == LAYOUT_COL2ROW_PRE)
+            load_tile_pre<V, E, P, SETS>(dst_v, at, src, t, sp);
+        else
+            load_tile<V, E, P, SETS>(dst_v, at, src, t, sp.s, sp.nt_load);
     };
     load(v, a);
 #pragma unroll
@@ -477,7 +478,8 @@ __global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()))
         V vn[SETS][E];
         TileLines<SETS> an;
         if (it + 1 < PIPE) {
-            an = tile_lines<L, LINES, SETS, LAYOUT>(order_tiles(vbid(it + 1), sp.ntiles, sp.order), c, sp);
+            an = tile_lines<L, LINES, SETS, LAYOUT>(order_tiles(vbid(it + 1), sp.ntiles, sp.order, sp.scatter), c,
+                                                    sp);
             load(vn, an);
         }
         if (it > 0) __syncthreads();  // the previous tile has finished with LDS
@@ -650,6 +652,12 @@ static hipError_t dispatch_logl(int layout, int lines, int sets, const StagePara
             if constexpr (EB == 8 && LOGL == 10 && C64_SHARED_LINES != WMIN && C64_SHARED_LINES != WMAX) {
                 if (lines == C64_SHARED_LINES && sets == 1)
                     return launch_one<T, LOGL, C64_SHARED_LINES, 1, LAYOUT_COL, EPC>(p, stream);
+            }
+        }
+        if (layout == LAYOUT_COL2ROW_PRE && sets == 1) {
+            if (lines == WMAX) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL2ROW_PRE, EPC>(p, stream);
+            if constexpr (WMIN != WMAX) {
+                if (lines == WMIN) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL2ROW_PRE, EPC>(p, stream);
             }
         }
         if (layout == LAYOUT_COL2ROW && sets == 1) {
