@@ -109,7 +109,8 @@ enum {
  * an M-point backward transform and a post-multiply pass.  When the M-point
  * transforms run out of place (the device has room for a second work array),
  * the pre-multiply and the pointwise product are applied by the first pass
- * of each transform as it loads, so they add no pass of their own.
+ * of each transform as it loads and the post-multiply by the last pass as it
+ * stores, so they add no pass of their own.
  */
 efft_plan_t *efft_plan(int64_t n, int dtype, int dir, int inplace);
 

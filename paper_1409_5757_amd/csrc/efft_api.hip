@@ -176,6 +176,7 @@ struct efft_plan_s {
     // chirp (forward) and the product with V (backward) done by the first
     // pass as it loads, so neither takes a pass of its own
     std::vector<Pass> chirp_fwd, chirp_bwd;
+    bool chirp_post;  // chirp_bwd's last pass also post-multiplies into the output
     // N = M * 2^s with a small odd M (KIND_MIXED): tables (W_M, lo, hi of W_N)
     // in `tables`, rows of 2^s points transformed by `inner` (batch M), work
     int m_odd, h_mixed;
@@ -425,7 +426,8 @@ int total_passes(const efft_plan_s *p)
 {
     if (p->kind == KIND_C2C) return int(p->passes.size());
     if (p->kind == KIND_CHIRP)  // (premul,) M-point forward, (product,) M-point backward, postmul
-        return int(p->inner->passes.size()) + int(p->inner2->passes.size()) + (p->chirp_fwd.empty() ? 3 : 1);
+        return int(p->inner->passes.size()) + int(p->inner2->passes.size()) +
+               (p->chirp_fwd.empty() ? 3 : p->chirp_post ? 0 : 1);
     if (p->kind == KIND_MIXED)  // radix-M pass, the rows' passes (and a reorder)
         return p->mixed_passes.empty() ? int(p->inner->passes.size()) + 2 : int(p->mixed_passes.size()) + 1;
     return int(p->inner->passes.size()) + 1;
@@ -462,7 +464,8 @@ int run_mixed(const efft_plan_s *p, const void *in, void *out, hipStream_t strea
 // Chirp plan: per signal, w = (x a) zero-padded; w = DFT_M(w); w *= V;
 // w = DFT_M^-(w) (the 1/M is in V); out = scale * a * w[0 .. N).  With
 // out-of-place M-point plans the first two products happen in the first
-// pass of each transform, as it loads.
+// pass of each transform, as it loads, and the last in the last pass of the
+// backward transform, as it stores.
 int run_chirp(const efft_plan_s *p, const void *in, void *out, hipStream_t stream, void **events, int nevents)
 {
     const int np = total_passes(p);
@@ -476,14 +479,17 @@ int run_chirp(const efft_plan_s *p, const void *in, void *out, hipStream_t strea
         char *y = static_cast<char *>(out) + b * p->n * p->eb;
         if (!p->chirp_fwd.empty()) {
             // x -> work2 (premultiplied and zero-padded as loaded), work2 ->
-            // work (times V as loaded), postmul work -> y
+            // work (times V as loaded; the last pass post-multiplies straight
+            // into y, else a post-multiply pass follows)
             int r = run_passes(p->chirp_fwd, 1, p->eb, x, p->work2, nullptr, stream, events, events ? nf + 1 : 0);
             if (r != EFFT_OK) return r;
-            r = run_passes(p->chirp_bwd, 1, p->eb, p->work2, p->work, nullptr, stream, events ? events + nf : nullptr,
+            std::vector<Pass> bwd = p->chirp_bwd;
+            if (p->chirp_post) bwd.back().sp.post_out = y;
+            r = run_passes(bwd, 1, p->eb, p->work2, p->work, nullptr, stream, events ? events + nf : nullptr,
                            events ? nb + 1 : 0);
             if (r != EFFT_OK) return r;
-            if (launch_postmul(p->eb, p->work, y, p->chirp, p->n, p->scale, stream) != hipSuccess ||
-                !rec(np))
+            if (!p->chirp_post &&
+                (launch_postmul(p->eb, p->work, y, p->chirp, p->n, p->scale, stream) != hipSuccess || !rec(np)))
                 return EFFT_ERR_HIP;
             continue;
         }
@@ -851,6 +857,14 @@ efft_plan_s *create_chirp(int64_t n, int64_t batch, int dtype, int dir, int inpl
         p->chirp_bwd.front().layout = LAYOUT_COL2ROW_PRE;
         p->chirp_bwd.front().sp.pmode = PRE_MUL;
         p->chirp_bwd.front().sp.pre = p->vhat;
+        Pass &last = p->chirp_bwd.back();
+        p->chirp_post = p->chirp_bwd.size() >= 2 && last.layout == LAYOUT_COL;
+        if (p->chirp_post) {
+            last.layout = LAYOUT_COL_POST;
+            last.sp.post = p->chirp;
+            last.sp.post_scale = p->scale;
+            last.sp.n_valid = n;
+        }
     }
     // V = DFT_M(v) / M, formed in the work array and transformed into vhat
     // (in place when the inner plans are)

@@ -13,9 +13,10 @@
 // every N >= 3 instead.
 //
 // With out-of-place M-point transforms, the pre-multiply and the product with
-// V are applied by the transposing first pass of each transform as it loads
-// (the same products as premul_kernel and pointwise_kernel below, which serve
-// the in-place transforms).
+// V are applied by the transposing first pass of each transform as it loads,
+// and the post-multiply by the last pass of the backward transform as it
+// stores (the same products as the kernels below, which serve the in-place
+// transforms).
 //
 // The chirp is exact in its phase: m^2 mod 2N is reduced in 128-bit integer
 // arithmetic, and a_m = exp(sign*pi*i * r/N), r = m^2 mod 2N, is evaluated in

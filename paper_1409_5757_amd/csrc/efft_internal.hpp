@@ -17,9 +17,12 @@ enum Layout : int {
     LAYOUT_ROW2COL = 3, // contiguous rows read from a scratch array, each
                         // written as a strided column of the output, in
                         // natural order (the last pass of a scratch plan)
-    LAYOUT_COL2ROW_PRE = 4  // LAYOUT_COL2ROW whose loads apply the factors of
+    LAYOUT_COL2ROW_PRE = 4, // LAYOUT_COL2ROW whose loads apply the factors of
                             // sp.pmode (separate kernels, so the plain
                             // transposing pass keeps its own code)
+    LAYOUT_COL_POST = 5     // LAYOUT_COL whose outputs n < n_valid go to
+                            // post_out times post_scale * post[n] (FP64), and
+                            // the others nowhere: the chirp path's last pass
 };
 
 // Twiddle applied to output k of line (block b, offset o) of a pass.
@@ -72,7 +75,10 @@ struct StageParams {
     int64_t row_mul;     // LAYOUT_COL2ROW: line o's row starts at row_mul * rev(o);
                          // LAYOUT_ROW2COL: column stride of the output
     const void *pre;     // LAYOUT_COL2ROW_PRE: factors applied on load (see PreMode)
-    int64_t n_valid;     // PRE_CHIRP: points of the source signal
+    int64_t n_valid;     // PRE_CHIRP: points of the source signal; LAYOUT_COL_POST: points kept
+    const void *post;    // LAYOUT_COL_POST: double2 factors (the chirp)
+    void *post_out;      // LAYOUT_COL_POST: destination of the n_valid kept points
+    double post_scale;   // LAYOUT_COL_POST: multiplies the factors
     int pmode;           // PreMode
     int64_t ilv;         // LAYOUT_ROW2COL: signals interleaved in the output (1: none).
                          // With ilv = M, bin k of signal b of each group of M signals
@@ -212,7 +218,8 @@ inline int col_order(int64_t stride) { return stride >= WIDE_TILE_STRIDE ? TILE_
 // complex64 (512-byte rows) lost 17% there and keeps 1031.
 inline int64_t scatter_stride(int layout, int lines, int sets, int dtype_bytes)
 {
-    return (layout == LAYOUT_COL && lines * sets * dtype_bytes == 256) ? 129 : 1031;
+    return ((layout == LAYOUT_COL || layout == LAYOUT_COL_POST) && lines * sets * dtype_bytes == 256) ? 129
+                                                                                                       : 1031;
 }
 
 // Lines per workgroup for complex64 lines of 1024 points at a small stride:

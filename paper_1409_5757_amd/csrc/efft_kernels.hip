@@ -326,6 +326,27 @@ __device__ __forceinline__ void load_tile_pre(V (&v)[SETS][E], const TileLines<S
     }
 }
 
+// The chirp path's last stores: point n = n0 + stride * i goes to
+// post_out[n] times post_scale * post[n] (FP64, rounded once; the product a
+// separate post-multiply pass computes) if n < n_valid, and nowhere else.
+template <typename V, int E>
+__device__ __forceinline__ void store_post(const V *w, int64_t n0, int64_t stride, const StageParams &sp)
+{
+    using T = decltype(V{}.x);
+    const double2 *c = static_cast<const double2 *>(sp.post);
+    V *out = static_cast<V *>(sp.post_out);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int64_t n = n0 + stride * i;
+        if (n < sp.n_valid) {
+            const double2 a = load_nt(c + n);
+            const double2 p = cmul(double2{double(w[i].x), double(w[i].y)},
+                                   double2{a.x * sp.post_scale, a.y * sp.post_scale});
+            store_nt(out + n, V{T(p.x), T(p.y)});
+        }
+    }
+}
+
 // Stores of E points of a thread, point i at p + stride * i.
 template <typename V, int E>
 __device__ __forceinline__ void store_points(V *p, int64_t stride, const V *w, int nt)
@@ -390,7 +411,10 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
                 apply_stage_twiddle<V, E, P>(v[st], t, g, sp.tw_scale, sp.tt);
             }
             finish_outputs<V, E>(v[st], sp);
-            store_points<V, E>(dst + a.base[st] + sp.s * int64_t(t), sp.s * int64_t(P), v[st], sp.nt_store);
+            if constexpr (LAYOUT == LAYOUT_COL_POST)
+                store_post<V, E>(v[st], a.base[st] + sp.s * int64_t(t), sp.s * int64_t(P), sp);
+            else
+                store_points<V, E>(dst + a.base[st] + sp.s * int64_t(t), sp.s * int64_t(P), v[st], sp.nt_store);
         }
     } else {
         // outputs land in LDS in natural order; re-read them one contiguous
@@ -608,7 +632,7 @@ static hipError_t launch_one(const StageParams &p, hipStream_t stream)
     // workgroups of at most 512 threads at 16 points per thread have room
     constexpr bool ROOM = SETS == 1 && EP == 16 && LINES * LineGeom<(1 << LOGL), EP>::P <= 512;
     constexpr int PIPE = !ROOM ? 1
-                         : (LAYOUT == LAYOUT_COL) ? EFFT_PIPE_COL
+                         : (LAYOUT == LAYOUT_COL || LAYOUT == LAYOUT_COL_POST) ? EFFT_PIPE_COL
                          : (LAYOUT == LAYOUT_ROW) ? EFFT_PIPE_ROW : EFFT_PIPE_X;
     if (PIPE > 1 && p.ntiles >= 64 * PIPE && p.ntiles % PIPE == 0)
         return launch_pipe<T, LOGL, LINES, SETS, LAYOUT, PIPE, EP>(p, stream);
@@ -652,6 +676,19 @@ static hipError_t dispatch_logl(int layout, int lines, int sets, const StagePara
             if constexpr (EB == 8 && LOGL == 10 && C64_SHARED_LINES != WMIN && C64_SHARED_LINES != WMAX) {
                 if (lines == C64_SHARED_LINES && sets == 1)
                     return launch_one<T, LOGL, C64_SHARED_LINES, 1, LAYOUT_COL, EPC>(p, stream);
+            }
+        }
+        if (layout == LAYOUT_COL_POST) {
+            if (lines == WMAX && sets == 1) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL_POST, EPC>(p, stream);
+            if constexpr (LOGL == 10 && EB == 16 && WMAX * EB == 128) {
+                if (lines == WMAX && sets == 2) return launch_one<T, LOGL, WMAX, 2, LAYOUT_COL_POST, EPC>(p, stream);
+            }
+            if constexpr (WMIN != WMAX) {
+                if (lines == WMIN && sets == 1) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL_POST, EPC>(p, stream);
+            }
+            if constexpr (EB == 8 && LOGL == 10 && C64_SHARED_LINES != WMIN && C64_SHARED_LINES != WMAX) {
+                if (lines == C64_SHARED_LINES && sets == 1)
+                    return launch_one<T, LOGL, C64_SHARED_LINES, 1, LAYOUT_COL_POST, EPC>(p, stream);
             }
         }
         if (layout == LAYOUT_COL2ROW_PRE && sets == 1) {
