@@ -263,7 +263,9 @@ int64_t efft_plan_bytes(const efft_plan_t *plan);
  * owns and keeps for its whole life (it allocates nothing at execution). */
 int64_t efft_workspace_bytes(const efft_plan_t *plan);
 
-/* Number of kernel launches one execution enqueues; -1 for a bad handle. */
+/* Number of kernel launches one execution enqueues (for a chirp-path plan,
+ * which runs the signals of a batch one after another, per signal); -1 for a
+ * bad handle. */
 int efft_plan_passes(const efft_plan_t *plan);
 
 /*
