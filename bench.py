@@ -15,7 +15,8 @@ ceiling, and the FP64 CPU oracle timed on a bounded sample on the host cores.
     python bench.py --workload c1|c3|c4|c5    # the other workloads, one line each:
         c1 2^20 complex128 out of place; c3 2^32 complex64 out of place;
         c4 2^34 complex64 in place, forward + inverse; c5 64 x 2^24 complex64
-        forward + loss + adjoint backward through autograd
+        forward + loss + adjoint backward through autograd; c2f32 the default
+        transform in complex64 alone
 """
 from __future__ import annotations
 
@@ -122,6 +123,20 @@ def copy_ceiling(nbytes: int) -> tuple[float, float]:
     return max(out[0], out[1]), out[2]
 
 
+def calibration_copy() -> None:
+    """One elementwise torch kernel over 2^26 doubles (torch.neg: 512 MiB read
+    + 512 MiB written, contiguous): the kernel of known traffic whose
+    FETCH_SIZE / WRITE_SIZE readings scale the counters of the transform's
+    passes."""
+    import torch
+    a = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+
+
 def cpu_baseline(budget_s: float = 12.0):
     """The FP64 oracle (radix-2, OpenMP) on 2^24-point transforms, repeated
     until the budget is used; GFLOP/s by the same 5 N log2 N count."""
@@ -176,6 +191,10 @@ OTHER_WORKLOADS = {
     "c5": ("64 signals of N=2^24 complex64 (8 GiB): y = FFT(x) through autograd, loss = sum |w*y - t|^2, "
            "backward through the hand-written adjoint; a step is forward + loss + backward",
            24, "complex64", False, 64),
+    # the FP32 companion of the default workload on its own (what the HBM
+    # byte counters of its passes are taken on)
+    "c2f32": ("forward in-place 1D C2C FFT, N=2^30 complex64 (8 GiB), uniform [-1,1) inputs in HBM",
+              30, "complex64", True, 1),
 }
 
 
@@ -206,7 +225,11 @@ def run_other(args) -> int:
         inputs.fill_uniform_torch(x, seed=0)
     flops = 5 * batch * n * q
     extra = {}
-    if args.workload in ("c1", "c3"):
+    if args.workload == "c2f32":
+        plan = api.Plan(n, dt, -1, True, device=dev)
+        ms_step, _, per_pass = time_transform(plan, x, args.steps, args.warmup)
+        plan.close()
+    elif args.workload in ("c1", "c3"):
         plan = api.Plan(n, dt, -1, False, device=dev)
         y = torch.empty_like(x)
         ms_step, _, per_pass = time_transform(plan, x, args.steps, args.warmup, out=y)
@@ -314,12 +337,17 @@ def main() -> int:
     ap.add_argument("--no-anylen", action="store_true")
     ap.add_argument("--workload", choices=sorted(OTHER_WORKLOADS) + ["c2"], default="c2",
                     help="c2 (default): the in-place 2^30 complex128 transform with its companions; "
-                         "c1, c3, c4, c5: the other workloads, one JSON line each")
+                         "c1, c3, c4, c5, c2f32: the other workloads, one JSON line each")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run one elementwise torch kernel over 512 MiB (the kernel of known "
+                         "traffic that scales the HBM byte counters) before the workload")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one transform on one GPU; runs on more than one GPU are not "
               "part of this benchmark (use --gpus 1)", file=sys.stderr)
         return 2
+    if args.calibrate:
+        calibration_copy()
     if args.workload != "c2":
         return run_other(args)
 

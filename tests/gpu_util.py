@@ -42,9 +42,11 @@ def run_library(x_host: np.ndarray, dtype, direction: int, inplace: bool, scale:
     return out.cpu().numpy(), x.cpu().numpy()
 
 
-def oracle_bins_from_device(x_dev: torch.Tensor, bins, sign: int = -1, chunk: int = 1 << 24):
+def oracle_bins_from_device(x_dev: torch.Tensor, bins, sign: int = -1, chunk: int = 1 << 24,
+                            progress_every: int = 1 << 31):
     """Eq. "eqf" at `bins` by the CPU oracle, streaming the device input to the
-    host chunk by chunk (the values are exactly those the transform reads)."""
+    host chunk by chunk (the values are exactly those the transform reads);
+    prints a progress line every `progress_every` input points."""
     import oracle
     n = x_dev.shape[0]
     acc = None
@@ -52,6 +54,8 @@ def oracle_bins_from_device(x_dev: torch.Tensor, bins, sign: int = -1, chunk: in
         m = min(chunk, n - s)
         h = x_dev[s:s + m].cpu().numpy()
         acc = oracle.dft_bins(h, bins, sign=sign, n=n, offset=s, acc=acc)
+        if (s + m) % progress_every == 0 and s + m < n:
+            print(f"  direct sum at {len(bins)} bins: {s + m} of {n} points", flush=True)
     return oracle.bins_value(acc)
 
 

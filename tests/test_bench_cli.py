@@ -30,12 +30,13 @@ def test_unknown_workload_is_rejected():
 
 def test_workload_table():
     w = bench.OTHER_WORKLOADS
-    assert sorted(w) == ["c1", "c3", "c4", "c5"]
+    assert sorted(w) == ["c1", "c2f32", "c3", "c4", "c5"]
     # (description, log2 N, dtype, in place, batch)
     assert (w["c1"][1], w["c1"][2], w["c1"][3], w["c1"][4]) == (20, "complex128", False, 1)
     assert (w["c3"][1], w["c3"][2], w["c3"][3], w["c3"][4]) == (32, "complex64", False, 1)
     assert (w["c4"][1], w["c4"][2], w["c4"][3], w["c4"][4]) == (34, "complex64", True, 1)
     assert (w["c5"][1], w["c5"][2], w["c5"][3], w["c5"][4]) == (24, "complex64", False, 64)
+    assert (w["c2f32"][1], w["c2f32"][2], w["c2f32"][3], w["c2f32"][4]) == (30, "complex64", True, 1)
 
 
 def test_roofline_fields():

@@ -1,0 +1,165 @@
+"""Dense-input parity on every bin at the smallest sizes whose plans run the
+kernel shapes of the full-size workloads.
+
+Every output of the transform is compared with the FP64 radix-2 oracle
+(Eq. "eqf" computed by Eqs. "eqct"/"eqctt") on i.i.d. uniform [-1, 1) inputs,
+forward and backward: relative L2 (Eq. "l2norm", read with squared moduli)
+against the workload bars (1e-12 complex128, 1e-5 complex64 against the FP64
+oracle) and the largest absolute error relative to the largest |F_k|.
+
+Which plan shape each size reaches (digits log2, planner's choice):
+
+* 2^28 complex128 in place, (10, 8, 10): the first pass takes two sets of 8
+  lines of 1024 points at a 2^18 stride (the 2^30 in-place first pass), the
+  row pass of 1024 points and the 64 x 64 tile swap; with a scratch array,
+  the row-to-column last pass of the 2^30 scratch schedule.
+* 2^28 complex128 out of place, (10, 9, 9): the transposing first pass of
+  1024-point lines at a 2^18 stride.
+* 2^28 complex64 in place, (10, 8, 10): 16 lines of 1024 points at a 2^18
+  stride (the 2^30 complex64 first pass).
+* 2^26 complex64 in place, (9, 8, 9): 32 lines of 512 points at a 2^17
+  stride (the 2^34 first pass).
+* 2^25 complex64 out of place, (9, 8, 8): 64 lines of 256 points at a 2^17
+  stride (the slowest 2^32 out-of-place pass, and the 2^34 second pass).
+
+The full 2^30 complex128 in-place spectrum of the benchmark's own plan is
+compared on every bin too when the host has the memory for three 16 GiB
+arrays; otherwise 256 sampled bins by the direct sum.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1409_5757_amd import _lib, api, inputs
+from tests.gpu_util import TOL, oracle_bins_from_device, rel_l2, max_abs, sample_bins
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+DEV = torch.device("cuda", 0)
+C128, C64 = torch.complex128, torch.complex64
+
+CASES = [  # (log2 N, dtype, in place, digits the planner must choose)
+    (28, C128, True, [10, 8, 10]),
+    (28, C128, False, [10, 9, 9]),
+    (28, C64, True, [10, 8, 10]),
+    (26, C64, True, [9, 8, 9]),
+    (25, C64, False, [9, 8, 8]),
+]
+
+
+def _compare(got: np.ndarray, ref: np.ndarray, chunk: int = 1 << 24):
+    """(relative L2, max abs error, max |ref|) over two host arrays, by chunks."""
+    num = den = 0.0
+    mabs = mref = 0.0
+    for s in range(0, ref.shape[0], chunk):
+        r = ref[s:s + chunk]
+        d = got[s:s + chunk].astype(np.complex128) - r
+        a = np.abs(d)
+        num += float(np.dot(a, a))
+        ar = np.abs(r)
+        den += float(np.dot(ar, ar))
+        mabs = max(mabs, float(a.max()))
+        mref = max(mref, float(ar.max()))
+    return (num / den) ** 0.5, mabs, mref
+
+
+def _host_memory_available() -> int:
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) * 1024
+    except OSError:
+        pass
+    return 0
+
+
+def _run(x_dev: torch.Tensor, direction: int, inplace: bool, scratch: bool = False) -> np.ndarray:
+    n = x_dev.shape[0]
+    plan = api.get_plan(n, x_dev.dtype, direction, inplace, 1.0, DEV)
+    if inplace:
+        sc = plan.make_scratch() if scratch else None
+        plan.execute(x_dev, scratch=sc)
+        torch.cuda.synchronize()
+        del sc
+        return x_dev.cpu().numpy()
+    y = torch.empty_like(x_dev)
+    keep = x_dev[:1 << 16].clone()
+    plan.execute(x_dev, out=y)
+    torch.cuda.synchronize()
+    assert torch.equal(x_dev[:1 << 16], keep), "out-of-place transform wrote its input"
+    return y.cpu().numpy()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("q,dtype,inplace,digits", CASES,
+                         ids=[f"2^{c[0]}-{'c128' if c[1] == C128 else 'c64'}-{'inplace' if c[2] else 'oop'}"
+                              for c in CASES])
+def test_dense_every_bin(q, dtype, inplace, digits):
+    n = 1 << q
+    eb = 16 if dtype == C128 else 8
+    assert _lib.schedule(n, 2 if dtype == C128 else 1, inplace)[0] == digits
+    torch.cuda.empty_cache()
+    x = torch.empty(n, dtype=dtype, device=DEV)
+    schedules = [False, True] if (inplace and dtype == C128) else [False]
+    for direction in (-1, 1):
+        seed = 100 + q + (0 if direction == -1 else 1)
+        inputs.fill_uniform_torch(x, seed=seed)
+        xh = x.cpu().numpy()
+        ref = oracle.fft(xh, direction)
+        for scratch in schedules:
+            if scratch:
+                inputs.fill_uniform_torch(x, seed=seed)
+            got = _run(x, direction, inplace, scratch)
+            err, mabs, mref = _compare(got, ref)
+            print(f"2^{q} {dtype} inplace={inplace} scratch={scratch} dir={direction:+d}: "
+                  f"rel_l2={err:.3e} max_abs={mabs:.3e} max|F|={mref:.3e} ({n * eb >> 20} MiB)", flush=True)
+            assert err <= TOL[dtype], err
+            assert mabs <= TOL[dtype] * mref, (mabs, mref)
+            del got
+            if not inplace:
+                np.testing.assert_array_equal(x[:1 << 20].cpu().numpy(), xh[:1 << 20])
+        del xh, ref
+    del x
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_c2_2p30_complex128_in_place_dense():
+    """The benchmark's plan (2^30 complex128 in place, forward) on a dense
+    uniform input: every bin against the radix-2 oracle when the host holds
+    three 16 GiB arrays, else 256 sampled bins by the direct sum."""
+    n = 1 << 30
+    torch.cuda.empty_cache()
+    x = torch.empty(n, dtype=C128, device=DEV)
+    inputs.fill_uniform_torch(x, seed=0)
+    plan = api.get_plan(n, C128, -1, True, 1.0, DEV)
+    need = 3 * n * 16 + (8 << 30)
+    avail = _host_memory_available()
+    if avail >= need:
+        xh = x.cpu().numpy()
+        print(f"C2 dense: oracle on all {n} bins ({avail >> 30} GiB host memory available)", flush=True)
+        ref = oracle.fft(xh, -1)
+        del xh
+        plan.execute(x)
+        torch.cuda.synchronize()
+        got = x.cpu().numpy()
+        err, mabs, mref = _compare(got, ref)
+        print(f"C2 every bin: rel_l2={err:.3e} max_abs={mabs:.3e} max|F|={mref:.3e}", flush=True)
+        del got, ref
+    else:
+        bins = sample_bins(n, 252, seed=2030)
+        print(f"C2 dense: {len(bins)} sampled bins by the direct sum "
+              f"(host has {avail >> 30} GiB, every bin needs {need >> 30})", flush=True)
+        ref = oracle_bins_from_device(x, bins)
+        plan.execute(x)
+        torch.cuda.synchronize()
+        got = x[torch.from_numpy(bins).to(DEV)].cpu().numpy()
+        err, mabs, mref = rel_l2(got, ref), max_abs(got, ref), float(np.abs(ref).max())
+        print(f"C2 {len(bins)} bins: rel_l2={err:.3e} max_abs={mabs:.3e} max|F|={mref:.3e}", flush=True)
+    assert err <= TOL[C128], err
+    assert mabs <= TOL[C128] * mref
+    del x
+    torch.cuda.empty_cache()
+

@@ -68,7 +68,7 @@ def test_c2_2p30_complex128_in_place_sampled_and_round_trip():
     x = torch.empty(n, dtype=torch.complex128, device=DEV)
     inputs.fill_uniform_torch(x, seed=0)
     bins = sample_bins(n, 12, seed=30)
-    ref = oracle_bins_from_device(x, bins)
+    ref = oracle_bins_from_device(x, bins)  # dense every-bin check: test_gpu_dense.py
     sumsq = _sumsq(x)
     plan = api.get_plan(n, torch.complex128, -1, True, 1.0, DEV)
     plan.execute(x)
@@ -124,14 +124,15 @@ def test_c2_2p30_complex128_tones_full_spectrum():
     assert perr < 1e-12 and rest < 1e-12
 
 
+@pytest.mark.timeout(600)
 def test_c3_2p32_complex64_out_of_place_vs_fp64_oracle():
     """N = 2^32 complex64, normal inputs, out of place: error against the FP64
-    oracle at sampled bins (relative L2 and max abs), Parseval, input kept."""
+    oracle at 64 sampled bins (relative L2 and max abs), Parseval, input kept."""
     n = 1 << 32
     torch.cuda.empty_cache()
     x = torch.empty(n, dtype=torch.complex64, device=DEV)
     inputs.fill_normal_torch(x, seed=3)
-    bins = sample_bins(n, 8, seed=32)
+    bins = sample_bins(n, 60, seed=32)
     ref = oracle_bins_from_device(x, bins)
     sumsq = _sumsq(x)
     probe = x[:4096].clone()
@@ -148,8 +149,9 @@ def test_c3_2p32_complex64_out_of_place_vs_fp64_oracle():
     assert torch.equal(x[:4096], probe)
 
 
+@pytest.mark.timeout(600)
 def test_c4_2p34_complex64_in_place_forward_and_inverse():
-    """N = 2^34 complex64 (128 GiB) in place, forward then inverse: sampled
+    """N = 2^34 complex64 (128 GiB) in place, forward then inverse: 16 sampled
     bins against the FP64 oracle and the round trip over the whole array."""
     n = 1 << 34
     torch.cuda.empty_cache()
@@ -158,7 +160,7 @@ def test_c4_2p34_complex64_in_place_forward_and_inverse():
         pytest.skip(f"needs {n * 8 / 2**30 + 8:.0f} GiB free on the device, have {free / 2**30:.0f}")
     x = torch.empty(n, dtype=torch.complex64, device=DEV)
     inputs.fill_uniform_torch(x, seed=4)
-    bins = sample_bins(n, 2, seed=34)
+    bins = sample_bins(n, 12, seed=34)
     ref = oracle_bins_from_device(x, bins, chunk=1 << 26)
     api.get_plan(n, torch.complex64, -1, True, 1.0, DEV).execute(x)
     torch.cuda.synchronize()
