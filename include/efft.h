@@ -225,6 +225,26 @@ int efft_exec_oop(const efft_plan_t *plan, const void *in, void *out, void *stre
  */
 int efft_exec_scratch(const efft_plan_t *plan, void *data, void *scratch, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * transform of efft_exec_scratch with the scratch array taken from a fixed
+ * array of EFFT_NOALLOC_SCRATCH_BYTES bytes that the library holds on each
+ * device it runs on, until the process ends.  This call allocates nothing
+ * and frees nothing; it needs batch * N * element bytes <= that size (else
+ * EFFT_ERR_SIZE, nothing enqueued; 2^22 complex128 or 2^23 complex64
+ * points), an in-place plan (else EFFT_ERR_PLAN_KIND), and the plan's device
+ * to be the current one (else EFFT_ERR_ARG).  Results are bit-identical to
+ * efft_exec_scratch.  Every call on one device shares that device's array:
+ * two calls whose executions overlap in time on one device (different
+ * streams, or different host threads) race and give undefined results; calls
+ * ordered on one stream are safe.  Nothing in the array needs clearing
+ * between calls: the first pass writes every element it later reads.  For
+ * plans that gain nothing from scratch this call is efft_exec.
+ */
+#define EFFT_NOALLOC_SCRATCH_BYTES (64LL << 20)
+int efft_exec_noalloc(const efft_plan_t *plan, void *data, void *stream);
+
 /* Scratch bytes efft_exec_scratch uses (0 if none helps); -1 for a bad handle. */
 int64_t efft_scratch_bytes(const efft_plan_t *plan);
 

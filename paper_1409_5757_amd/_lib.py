@@ -59,6 +59,8 @@ def _bind(lib):
     lib.efft_exec_events.restype = ci
     lib.efft_exec_scratch.argtypes = [vp, vp, vp, vp]
     lib.efft_exec_scratch.restype = ci
+    lib.efft_exec_noalloc.argtypes = [vp, vp, vp]
+    lib.efft_exec_noalloc.restype = ci
     lib.efft_scratch_bytes.argtypes = [vp]
     lib.efft_scratch_bytes.restype = i64
     lib.efft_plan_passes_scratch.argtypes = [vp]

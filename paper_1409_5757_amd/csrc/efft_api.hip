@@ -185,6 +185,7 @@ struct efft_plan_s {
     // the rows interleaved into the output (natural order, times scale); empty
     // when the rows take one pass (then a reorder pass follows them)
     std::vector<Pass> mixed_passes;
+    int device;  // HIP device current when the plan was made (its tables live there)
 };
 
 namespace {
@@ -882,8 +883,45 @@ efft_plan_s *create_chirp(int64_t n, int64_t batch, int dtype, int dir, int inpl
 
 void register_plan(efft_plan_s *p)
 {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        dev = -1;
+    }
+    p->device = dev;
     std::lock_guard<std::mutex> lk(g_reg_mu);
     g_registry.insert(p);
+}
+
+// ------------------------------------------------ fixed device scratch array
+// The scratch array of efft_exec_noalloc: a fixed device array in place of
+// the caller-owned one of efft_exec_scratch, for callers that cannot
+// allocate.  Each device the library runs on holds its own copy for the life
+// of the process.  Host code never passes the array's name to a kernel (on
+// the host it only stands for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device on the first efft_exec_noalloc call there.
+static __device__ __align__(256) unsigned char scratch[EFFT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of the fixed scratch array on `dev` (the current device)
+int fixed_scratch(int dev, void **ptr)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return EFFT_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *a = nullptr;
+        if (hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)) != hipSuccess || !a) {
+            (void)hipGetLastError();
+            return EFFT_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = a;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return EFFT_OK;
 }
 
 // bytes of the input and output arrays of one execution
@@ -1054,6 +1092,28 @@ int efft_exec_scratch(const efft_plan_t *plan, void *data, void *scratch, void *
     v = validate_scratch(p, data, scratch);
     if (v != EFFT_OK) return v;
     return run_passes(p->scratch_passes, p->batch, p->eb, data, data, scratch, static_cast<hipStream_t>(stream),
+                      nullptr, 0);
+}
+
+int efft_exec_noalloc(const efft_plan_t *plan, void *data, void *stream)
+{
+    const efft_plan_s *p = live(plan);
+    if (!p) return plan ? EFFT_ERR_BADPLAN : EFFT_ERR_NULLPTR;
+    if (!p->inplace) return EFFT_ERR_PLAN_KIND;
+    const int v = validate_ptr(p, data);
+    if (v != EFFT_OK) return v;
+    if (p->scratch_passes.empty()) return run(p, data, data, static_cast<hipStream_t>(stream), nullptr, 0);
+    if (p->batch * p->n * p->eb > int64_t(EFFT_NOALLOC_SCRATCH_BYTES)) return EFFT_ERR_SIZE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return EFFT_ERR_HIP;
+    }
+    if (dev != p->device) return EFFT_ERR_ARG;
+    void *ws = nullptr;
+    const int r = fixed_scratch(dev, &ws);
+    if (r != EFFT_OK) return r;
+    return run_passes(p->scratch_passes, p->batch, p->eb, data, data, ws, static_cast<hipStream_t>(stream),
                       nullptr, 0);
 }
 
