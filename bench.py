@@ -37,7 +37,7 @@ METRIC = "1D C2C FFT GFLOP/s (5N·log2N/t) + HBM GB/s % peak, FP64 vs FP32"
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("efft_kernels.hip", "efft_device.hpp", "efft_internal.hpp", "efft_api.hip"):
+    for f in ("efft_kernels.hip", "efft_stage.hpp", "efft_device.hpp", "efft_internal.hpp", "efft_api.hip"):
         with open(os.path.join(ROOT, "paper_1409_5757_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

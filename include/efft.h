@@ -29,16 +29,24 @@
  *
  * Memory: every data pointer is a device pointer in the calling process's
  * current HIP device, owned by the caller, and must be aligned to one element
- * (8 bytes for EFFT_C64, 16 for EFFT_C128).  A plan owns only its FP64
- * twiddle tables (a few MiB at most), allocated on the device that is current
- * when the plan is created; efft_destroy frees them.
+ * (8 bytes for EFFT_C64, 16 for EFFT_C128).  The paper's EFFT allocates its
+ * own 64-byte-aligned array (Section 3.1); here the caller allocates, and the
+ * kernels need only element alignment.  A power-of-two or real-data plan owns only its FP64 twiddle
+ * tables (at most a few hundred KiB); a plan for another length also owns
+ * work arrays (see efft_plan and efft_plan_bytes).  Everything a plan owns is
+ * allocated on the device that is current when the plan is created, and
+ * efft_destroy frees it.
  *
- * Asynchrony and threads: efft_exec / efft_exec_oop only enqueue kernels on
- * the given stream (a hipStream_t; NULL selects the default stream) and
- * return; device-side faults surface at the caller's next synchronisation.
- * A plan is immutable after creation and may be executed concurrently from
- * several streams, since it holds no scratch memory.  Error statuses from
- * efft_plan are kept per host thread (efft_last_error).
+ * Asynchrony and threads: the exec calls only enqueue kernels on the given
+ * stream (a hipStream_t; NULL selects the default stream) and return;
+ * device-side faults surface at the caller's next synchronisation.  Plan
+ * creation waits for its own table-building kernels on a private stream of
+ * the library (no device-wide synchronisation).  A power-of-two or real-data
+ * plan holds no scratch memory and may be executed concurrently from several
+ * streams; a plan that owns work arrays (lengths that are not powers of two)
+ * must not have two executions in flight at once.  efft_set_pass_options
+ * changes a plan and must not overlap any execution of it.  Error statuses
+ * from plan creation are kept per host thread (efft_last_error).
  *
  * Errors: every function that returns int returns EFFT_OK (0) or one of the
  * negative EFFT_ERR_* codes below; efft_strerror names them.
@@ -144,7 +152,7 @@ int64_t efft_plan_batch(const efft_plan_t *plan);
  * first) instead of by the planner -- the GPU form of the paper's tuning
  * scan over the number of splits (Section 5.2, Fig. "fig:heatmap"; see
  * efft_set_pass_options for the other knobs).  The digits must sum to q;
- * with m = 1, q <= 12; with m > 1 every digit lies in [4, 10] and an in-place
+ * with m = 1, q <= 12; with m > 1 every digit lies in [4, 12] and an in-place
  * plan needs a palindrome (d_i = d_{m-1-i}).  Returns NULL with EFFT_ERR_ARG
  * for an unusable decomposition, EFFT_ERR_NULLPTR if log2_digits is NULL, and
  * the codes of efft_plan_many otherwise.
@@ -197,9 +205,16 @@ efft_plan_t *efft_plan_real(int64_t n, int dtype, int dir, double scale);
 
 /*
  * In-place transform of data[0 .. N) (device pointer, N elements of the
- * plan's dtype), enqueued on stream.  The in-place path is a sequence of
- * batched sub-FFT passes followed by one tiled digit-reversal pass; it needs
- * no memory beyond the data array itself.
+ * plan's dtype), enqueued on stream: the compute step of the paper's
+ * create/commit/compute flow (Section 2.1, Listing "code:dfti",
+ * DftiComputeForward) and of EFFT_Transform's RunTransform() (Section 4,
+ * Listing "code:efftheader"), with the result in the data array itself.  The
+ * in-place path is a sequence of batched sub-FFT passes followed by one tiled
+ * digit-reversal pass; it needs no memory beyond the data array itself.
+ * EFFT_ERR_NULLPTR for a NULL plan or data, EFFT_ERR_BADPLAN for a handle
+ * that is not a live plan, EFFT_ERR_PLAN_KIND for an out-of-place plan,
+ * EFFT_ERR_ALIGN for data not aligned to one element, EFFT_ERR_HIP if a
+ * launch fails; nothing is enqueued on an argument error.
  */
 int efft_exec(const efft_plan_t *plan, void *data, void *stream);
 
@@ -264,8 +279,13 @@ int efft_plan_passes_scratch(const efft_plan_t *plan);
 int efft_exec_events(const efft_plan_t *plan, const void *in, void *out, void *scratch, void *stream,
                      void **events, int nevents);
 
-/* Free the plan's device tables; NULL is a no-op returning EFFT_OK; a handle
- * that is not a live plan (already destroyed) returns EFFT_ERR_BADPLAN. */
+/* Free everything the plan owns on the device (its tables and, for lengths
+ * that are not powers of two, its work arrays), as the paper's
+ * ~EFFT_Transform() releases the transform's buffers (Section 4, Listing
+ * "code:efftheader").
+ * The caller must make sure no execution of the plan is still running.  NULL
+ * is a no-op returning EFFT_OK; a handle that is not a live plan (already
+ * destroyed) returns EFFT_ERR_BADPLAN. */
 int efft_destroy(efft_plan_t *plan);
 
 /* Status of the last efft_plan call on this host thread. */

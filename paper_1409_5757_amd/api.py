@@ -22,6 +22,7 @@ autograd: grad_x = A^H grad_y).
 """
 from __future__ import annotations
 
+import collections
 import ctypes
 import threading
 
@@ -192,6 +193,9 @@ class RealPlan:
                                              ctypes.c_void_p(out.data_ptr()), None, s, arr, len(events)),
                    "efft_exec_events")
 
+    def device_bytes(self) -> int:
+        return int(self.lib.efft_plan_bytes(self.handle))
+
     def close(self) -> None:
         h = getattr(self, "handle", None)
         if h is not None and h.value:
@@ -205,25 +209,55 @@ class RealPlan:
             pass
 
 
-_cache: dict = {}
+# Plans made by the functional calls (fft, ifft, ...) are kept for reuse, the
+# most recently used last.  The cache is bounded by a count and by the device
+# bytes its plans hold (plans for lengths that are not powers of two own work
+# arrays as large as the signal); the least recently used plans go first, after
+# a synchronisation of their device, since work may still be queued on them.
+# Plans are created (allocated) on first use: code that captures a HIP graph
+# should make its plans before the capture, e.g. by one eager call or with Plan.
+_cache: "collections.OrderedDict" = collections.OrderedDict()
 _cache_lock = threading.Lock()
+CACHE_MAX_PLANS = 64
+CACHE_MAX_BYTES = 8 << 30
+
+
+def _owns_work_arrays(n: int) -> bool:
+    return n >= 3 and (n & (n - 1)) != 0
+
+
+def _evict_locked() -> None:
+    total = sum(p.device_bytes() for p in _cache.values())
+    while _cache and (len(_cache) > CACHE_MAX_PLANS or total > CACHE_MAX_BYTES):
+        _, old = _cache.popitem(last=False)
+        total -= old.device_bytes()
+        torch.cuda.synchronize(old.device)
+        old.close()
 
 
 def get_plan(n: int, dtype: torch.dtype, direction: int, inplace: bool, scale: float,
              device: torch.device, batch: int = 1) -> Plan:
-    """Cached plan keyed by (N, batch, dtype, direction, in place, scale, device)."""
+    """Cached plan keyed by (N, batch, dtype, direction, in place, scale,
+    device), and for lengths that are not powers of two also by the current
+    stream: such plans own work arrays, so two streams must not share one."""
     key = (int(n), int(batch), dtype, int(direction), bool(inplace), float(scale), device)
+    if _owns_work_arrays(int(n)):
+        key += (torch.cuda.current_stream(device).cuda_stream,)
     with _cache_lock:
         p = _cache.get(key)
         if p is None:
             p = Plan(n, dtype, direction, inplace, scale, device, batch)
             _cache[key] = p
+            _evict_locked()
+        else:
+            _cache.move_to_end(key)
         return p
 
 
 def clear_plan_cache() -> None:
     with _cache_lock:
         for p in _cache.values():
+            torch.cuda.synchronize(p.device)
             p.close()
         _cache.clear()
 
@@ -286,6 +320,9 @@ def get_real_plan(n: int, real_dtype: torch.dtype, direction: int, scale: float,
         if p is None:
             p = RealPlan(n, real_dtype, direction, scale, device)
             _cache[key] = p
+            _evict_locked()
+        else:
+            _cache.move_to_end(key)
         return p
 
 

@@ -59,6 +59,12 @@ bool registered(const void *p)
 // largest line (log2) per layout: strided lines are limited by LDS for a
 // W-line tile, contiguous lines by LDS for one line
 int col_max(int dtype_bytes) { return dtype_bytes == 16 ? 10 : 10; }
+// largest strided digit of a caller-chosen decomposition
+int col_max_digits(int dtype_bytes)
+{
+    (void)dtype_bytes;
+    return STRIDED_LOGL_MAX;
+}
 int row_max(int dtype_bytes) { return dtype_bytes == 16 ? 12 : 12; }
 
 int log2_exact(int64_t n)
@@ -555,6 +561,7 @@ int run_passes(const std::vector<Pass> &passes, int64_t batch, int eb, const voi
             ps.sp.src = bufs[ps.src];
             ps.sp.dst = bufs[ps.dst];
             ps.sp.scatter = scatter_stride(ps.layout, ps.lines, ps.sets, eb);
+            ps.sp.off32 = EFFT_WAVE_UNIFORM && wave_offset_fits(ps.layout, ps.lines, ps.sp.s, eb) ? 1 : 0;
             e = launch_stage(eb, ps.layout, ps.logl, ps.lines, ps.sets, ps.sp, stream);
         }
         if (e != hipSuccess) return EFFT_ERR_HIP;
@@ -589,29 +596,72 @@ int validate_args(int q, int dtype, int dir, double scale)
     return EFFT_OK;
 }
 
-// Two-level FP64 table of W_N^m for N = 2^q on the current device:
-// lo[2^h], hi[2^(q-h)], h = ceil(q/2).
+// A private non-blocking stream for the kernels that build a plan's tables:
+// plan creation waits for them without synchronising the whole device, so
+// work on the caller's other streams keeps running.
+struct SetupStream {
+    hipStream_t s = nullptr;
+    bool ok;
+    SetupStream() { ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess; }
+    ~SetupStream()
+    {
+        if (s) (void)hipStreamDestroy(s);
+    }
+    // wait for everything enqueued; false if creation, a launch or the wait failed
+    bool finish(bool launched)
+    {
+        const bool done = ok && hipStreamSynchronize(s) == hipSuccess;
+        if (!(done && launched)) (void)hipGetLastError();
+        return done && launched;
+    }
+};
+
+// FP64 table of W_N^m for N = 2^q on the current device: two levels,
+// lo[2^h] and hi[2^(q-h)] with h = ceil(q/2) (and mid = {1}), or from
+// q = TW3_MIN_Q on three, lo[2^h], mid[2^h] and hi[2^(q-2h)] with
+// h = ceil(q/3) (see TwTable).
+// Built on a stream of the library's own, which the call waits for (the
+// tables must be complete before the plan is returned), so that other streams
+// of the device keep running.
 int make_tables(efft_plan_s *p, int q, TwTable *tt)
 {
-    const int h = (q + 1) / 2;
-    const int64_t n_lo = int64_t(1) << h, n_hi = int64_t(1) << (q - h);
-    p->table_bytes = (n_lo + n_hi) * int64_t(sizeof(double2));
+    const bool three = q >= TW3_MIN_Q;
+    const int h = three ? (q + 2) / 3 : (q + 1) / 2;
+    const int64_t n_lo = int64_t(1) << h;
+    const int64_t n_mid = three ? n_lo : 1;  // two levels: mid = {1}
+    const int64_t n_hi = int64_t(1) << (q - (three ? 2 * h : h));
+    // the FP32 line table (LINE_TW_N float2) follows the FP64 tables
+    p->table_bytes = (n_lo + n_mid + n_hi) * int64_t(sizeof(double2)) + LINE_TW_N * int64_t(sizeof(float2));
     if (hipMalloc(reinterpret_cast<void **>(&p->tables), size_t(p->table_bytes)) != hipSuccess) {
         (void)hipGetLastError();
         p->tables = nullptr;
         return EFFT_ERR_ALLOC;
     }
-    if (launch_twiddle_table(p->tables, n_lo, p->tables + n_lo, n_hi, h, q, nullptr) != hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess) {
+    double2 *lo = p->tables, *mid = lo + n_lo, *hi = mid + n_mid;
+    float2 *line32 = reinterpret_cast<float2 *>(hi + n_hi);
+    SetupStream ss;
+    // lo[j] = W^j and mid[j] = W^(j 2^h) (or hi[j] = W^(j 2^h) for two levels);
+    // for three levels then hi[j] = W^(j 2^(2h)); for two, mid[0] = W^0 = 1
+    bool launched = ss.ok &&
+                    launch_twiddle_table(lo, n_lo, three ? mid : hi, three ? n_mid : n_hi, h, q, ss.s) == hipSuccess;
+    if (launched)
+        launched = (three ? launch_twiddle_table(nullptr, 0, hi, n_hi, 2 * h, q, ss.s)
+                          : launch_twiddle_table(mid, 1, nullptr, 0, h, q, ss.s)) == hipSuccess;
+    if (launched) launched = launch_line32_table(line32, ss.s) == hipSuccess;
+    if (!ss.finish(launched)) {
         (void)hipFree(p->tables);
         p->tables = nullptr;
         return EFFT_ERR_HIP;
     }
-    tt->lo = p->tables;
-    tt->hi = p->tables + n_lo;
+    tt->lo = lo;
+    tt->hi = hi;
+    tt->mid = mid;
     tt->h = h;
+    tt->h2 = three ? 2 * h : h;
     tt->mask_n = (uint64_t(1) << q) - 1u;
     tt->mask_lo = uint64_t(n_lo) - 1u;
+    tt->mask_mid = three ? uint64_t(n_lo) - 1u : 0;
+    tt->line32 = line32;
     return EFFT_OK;
 }
 
@@ -632,7 +682,7 @@ bool kernels_exist(const efft_plan_s *p)
 }
 
 // A caller-chosen decomposition: log2 digits summing to q, each strided
-// digit within the strided kernels' range [4, col_max], a one-digit plan
+// digit within the strided kernels' range [4, STRIDED_LOGL_MAX], a one-digit plan
 // within the row kernels' range, and palindromic for an in-place plan (the
 // digit-reversal swap needs it).
 bool digits_usable(int q, int eb, int inplace, const int *d, int m)
@@ -643,7 +693,7 @@ bool digits_usable(int q, int eb, int inplace, const int *d, int m)
     if (sum != q) return false;
     if (m == 1) return q <= row_max(eb);
     for (int i = 0; i < m; ++i) {
-        if (d[i] < 4 || d[i] > col_max(eb)) return false;
+        if (d[i] < 4 || d[i] > col_max_digits(eb)) return false;
         if (inplace && d[i] != d[m - 1 - i]) return false;
     }
     return true;
@@ -710,7 +760,8 @@ int64_t tiles_for(const efft_plan_s *p, const Pass &ps, int lines, int sets)
     const int64_t nlines = p->n >> ps.logl;  // lines per signal
     const int64_t w = int64_t(lines) * sets;
     if (w < 1 || nlines % w) return -1;
-    if (ps.layout == LAYOUT_COL && ps.sp.s % w) return -1;  // a tile stays inside one block
+    if (ps.layout != LAYOUT_ROW && ps.layout != LAYOUT_ROW2COL && ps.sp.s % w)
+        return -1;  // a tile of strided lines stays inside one block
     return nlines / w * p->batch;
 }
 
@@ -786,9 +837,9 @@ efft_plan_s *create_mixed(int64_t n, int64_t batch, int dtype, int dir, int inpl
         *status = EFFT_ERR_ALLOC;
         return nullptr;
     }
-    if (launch_mixed_tables(p->tables, mo, p->tables + mo, n_lo, p->tables + mo + n_lo, n_hi, p->h_mixed, n,
-                            nullptr) != hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess) {
+    SetupStream ss;
+    if (!ss.finish(ss.ok && launch_mixed_tables(p->tables, mo, p->tables + mo, n_lo, p->tables + mo + n_lo, n_hi,
+                                                p->h_mixed, n, ss.s) == hipSuccess)) {
         free_plan(p);
         *status = EFFT_ERR_HIP;
         return nullptr;
@@ -870,9 +921,10 @@ efft_plan_s *create_chirp(int64_t n, int64_t batch, int dtype, int dir, int inpl
     // V = DFT_M(v) / M, formed in the work array and transformed into vhat
     // (in place when the inner plans are)
     void *vsrc = oop ? p->work : p->vhat;
-    if (launch_chirp(p->chirp, n, dir, nullptr) != hipSuccess ||
-        launch_chirp_v(p->eb, vsrc, p->chirp, n, m, nullptr) != hipSuccess ||
-        run_c2c(p->inner, vsrc, p->vhat, nullptr, nullptr, 0) != EFFT_OK || hipDeviceSynchronize() != hipSuccess) {
+    SetupStream ss;
+    if (!ss.finish(ss.ok && launch_chirp(p->chirp, n, dir, ss.s) == hipSuccess &&
+                   launch_chirp_v(p->eb, vsrc, p->chirp, n, m, ss.s) == hipSuccess &&
+                   run_c2c(p->inner, vsrc, p->vhat, ss.s, nullptr, 0) == EFFT_OK)) {
         free_plan(p);
         *status = EFFT_ERR_HIP;
         return nullptr;

@@ -137,22 +137,76 @@ template <typename V> __device__ __forceinline__ void store_nt(V *p, V v)
     __builtin_nontemporal_store(r, reinterpret_cast<native2 *>(p));
 }
 
+// Wave-uniform addressing: a pointer that is the same in every lane, moved
+// into scalar registers, plus a lane's 32-bit byte offset.  The loads and
+// stores then take the scalar-base form (one offset register shared by all
+// of a thread's accesses) instead of one 64-bit address register each.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+
+template <typename V> __device__ __forceinline__ gptr<V> wave_uniform(const V *p)
+{
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+    return reinterpret_cast<gptr<V>>((uint64_t(hi) << 32) | lo);
+}
+
+template <typename V> __device__ __forceinline__ gptr<V> at_offset(gptr<V> base, uint32_t byte_off)
+{
+    return reinterpret_cast<gptr<V>>(reinterpret_cast<gptr<char>>(base) + byte_off);
+}
+
+template <typename V> __device__ __forceinline__ V load_g(gptr<V> p, int nt)
+{
+    using T = decltype(V{}.x);
+    typedef T native2 __attribute__((ext_vector_type(2)));
+    const gptr<const native2> q = reinterpret_cast<gptr<const native2>>(p);
+    const native2 r = nt ? __builtin_nontemporal_load(q) : *q;
+    return V{r.x, r.y};
+}
+
+template <typename V> __device__ __forceinline__ void store_g(gptr<V> p, V v, int nt)
+{
+    using T = decltype(V{}.x);
+    typedef T native2 __attribute__((ext_vector_type(2)));
+    const native2 r = {v.x, v.y};
+    const gptr<native2> q = reinterpret_cast<gptr<native2>>(p);
+    if (nt)
+        __builtin_nontemporal_store(r, q);
+    else
+        *q = r;
+}
+
 // ---------------------------------------------------------------- twiddles
-// Two-level FP64 table of W_N^m = exp(-2*pi*i*m/N): W_N^m = hi[m >> h] * lo[m & (2^h - 1)].
+// FP64 table of W_N^m = exp(-2*pi*i*m/N) in three levels,
+//   W_N^m = (hi[m >> h2] * mid[(m >> h) & mask_mid]) * lo[m & (2^h - 1)].
+// For moderate N it is two levels in effect: h2 = h, mask_mid = 0 and mid[0]
+// = 1 exactly, so the middle product changes no bit; for large N, h2 = 2h and
+// mid[j] = W_N^(j 2^h), which keeps the tables a few hundred KiB (cached
+// while the data streams past) where two levels would need MiBs.  One lookup
+// path for both keeps the kernels free of a branch on the table shape.
 struct TwTable {
     const double2 *lo;
     const double2 *hi;
-    uint64_t mask_n;   // N - 1
-    uint64_t mask_lo;  // 2^h - 1
+    uint64_t mask_n;    // N - 1
+    uint64_t mask_lo;   // 2^h - 1
     int h;
+    const double2 *mid;
+    uint64_t mask_mid;  // 2^h - 1, or 0 (mid[0] = 1)
+    int h2;
+    const float2 *line32;  // W_4096^e, e < 4096, rounded once to FP32 (complex64 in-line twiddles)
 };
+
+// entries of the FP32 line table (the longest line a pass transforms)
+constexpr int LINE_TW_N = 4096;
 
 __device__ __forceinline__ double2 tw_lookup(const TwTable &tt, uint64_t m)
 {
     m &= tt.mask_n;
-    const double2 a = tt.hi[m >> tt.h];
-    const double2 b = tt.lo[m & tt.mask_lo];
-    return cmul(a, b);
+    const double2 a = tt.hi[m >> tt.h2];
+    const double2 b = tt.mid[(m >> tt.h) & tt.mask_mid];
+    const double2 c = tt.lo[m & tt.mask_lo];
+    return cmul(cmul(a, b), c);
 }
 
 template <typename V> __device__ __forceinline__ V round_tw(double2 w)

@@ -94,7 +94,34 @@ struct StageParams {
     int64_t scatter;     // TILE_XCD_SCATTER: odd stride, in tiles, of each XCD's walk
     int nt_load;         // 1: data loads carry the non-temporal (streaming) hint
     int nt_store;        // 1: data stores carry it
+    int off32;           // strided layouts: a lane's offset within its wave's rows fits 32 bits
+                         // (set by the launcher; see wave_offset_fits)
 };
+
+// Strided tiles address point i of a lane as a wave-uniform row base plus the
+// lane's offset c + s * (t - t0) within its wave (t0 the wave's first t): the
+// base lives in scalar registers and every load and store of the lane shares
+// one 32-bit offset register, so a tile's 16 to 32 loads can be in flight
+// without a 64-bit address register each.  That needs the offset below 2^32
+// bytes, which holds for every plan of the workloads; other plans take 64-bit
+// addresses.
+// Measured on gfx950 (2^30 points in place, first pass): complex64 gains
+// (5.75 -> 5.58 ms with two line sets), complex128 loses (8.08 -> 9.00 ms),
+// so complex128 keeps 64-bit addresses.
+#ifndef EFFT_WAVE_UNIFORM
+#define EFFT_WAVE_UNIFORM 1
+#endif
+#ifndef EFFT_WAVE_UNIFORM_C128
+#define EFFT_WAVE_UNIFORM_C128 0
+#endif
+inline bool wave_offset_fits(int layout, int lines, int64_t s, int dtype_bytes)
+{
+    if (layout == LAYOUT_ROW || layout == LAYOUT_ROW2COL) return false;
+    if (dtype_bytes == 16 && !EFFT_WAVE_UNIFORM_C128) return false;
+    const int64_t rows = lines >= 64 ? 1 : 64 / lines;  // distinct t in one wave
+    const int64_t bound = (int64_t(lines) + s * (rows - 1)) * dtype_bytes;
+    return bound < (int64_t(1) << 31);
+}
 
 // Tiled in-place digit reversal of a [R][M][R] array: element (a, mu, b)
 // swaps with (b, rev(mu), a).
@@ -130,6 +157,8 @@ hipError_t launch_stage(int dtype_bytes, int layout, int logl, int lines, int se
 hipError_t launch_swap(int dtype_bytes, const SwapParams &p, int64_t batch, hipStream_t stream);
 hipError_t launch_twiddle_table(double2 *lo, int64_t n_lo, double2 *hi, int64_t n_hi, int h,
                                 int q, hipStream_t stream);
+// W_4096^e in FP32 for e < LINE_TW_N
+hipError_t launch_line32_table(float2 *t, hipStream_t stream);
 hipError_t launch_r2c_post(int dtype_bytes, void *z, int64_t h, const TwTable &tt, double scale,
                            int apply_scale, hipStream_t stream);
 hipError_t launch_c2r_pre(int dtype_bytes, const void *f, void *z, int64_t h, const TwTable &tt,
@@ -159,6 +188,15 @@ hipError_t launch_reorder_m(int dtype_bytes, int m, const void *w, void *out, in
 // while on (per host thread), launch_stage / launch_swap only check that a
 // kernel exists for the arguments and launch nothing
 void set_dry_run(bool on);
+
+// Smallest q whose twiddle table takes three levels: two levels at q = 34
+// need 4 MiB, as much as one XCD's L2, and the first pass of 2^34 complex64
+// then read 1.46x its bytes from HBM (table misses); three levels at q >= 33
+// take at most 144 KiB.
+#ifndef EFFT_TW3_MIN_Q
+#define EFFT_TW3_MIN_Q 33
+#endif
+constexpr int TW3_MIN_Q = EFFT_TW3_MIN_Q;
 
 // LDS budget of one workgroup tile (one workgroup per CU on gfx950's 160 KB)
 constexpr int TILE_LDS_BYTES = 143360;
@@ -198,6 +236,19 @@ __host__ __device__ constexpr int col_lines_max(int dtype_bytes, int logl)
 }
 // the narrow tile: one 128-byte segment per row
 __host__ __device__ constexpr int col_lines_min(int dtype_bytes) { return dtype_bytes == 16 ? 8 : 16; }
+// the narrow tile of a line length: lines of 2^11 and 2^12 points fill the
+// LDS with fewer lines than one 128-byte segment
+__host__ __device__ constexpr int col_lines_narrow(int dtype_bytes, int logl)
+{
+    return col_lines_min(dtype_bytes) < col_lines_max(dtype_bytes, logl) ? col_lines_min(dtype_bytes)
+                                                                          : col_lines_max(dtype_bytes, logl);
+}
+
+// Longest strided line (log2) the kernels hold: 2^12 points, 4 complex64 or
+// 2 complex128 lines per tile (32-byte tile rows).  The planner's own
+// decompositions keep strided digits at 2^10 or less (wider tile rows); a
+// caller-chosen decomposition may use up to 2^12.
+constexpr int STRIDED_LOGL_MAX = 12;
 
 // Measured on gfx950: a pass that reads and writes the same strided lines
 // gains from long tile rows only at large strides (at a 2^24-element stride
@@ -236,23 +287,34 @@ inline int col_lines(int dtype_bytes, int logl, int64_t stride, bool same_positi
     const int w = col_lines_max(dtype_bytes, logl);
     if (same_positions && stride >= WIDE_TILE_STRIDE && stride >= w) return w;
     if (column_pass && dtype_bytes == 8 && logl == 10 && stride >= C64_SHARED_LINES) return C64_SHARED_LINES;
-    return col_lines_min(dtype_bytes);
+    return col_lines_narrow(dtype_bytes, logl);
 }
 
 // Line sets per workgroup of LAYOUT_COL passes: where even the widest tile of
-// 1024-point complex128 lines is a single 128-byte segment (8 lines), a second
-// set loaded together makes each tile row a 256-byte run at large strides; the
-// register file has room for it with 512 threads (not for complex64 tiles,
-// whose second set spills).
+// 1024-point lines is a single 128-byte segment (8 complex128 or 16 complex64
+// lines), a second set loaded together makes each tile row a 256-byte run at
+// large strides.  The register file has room for it: 512 threads of 199
+// VGPRs (complex128), 1024 threads of 122 (complex64).  At these strides
+// every tile row is a separate address translation, so the longer runs also
+// halve the translations per byte.
 #ifndef EFFT_COL_SETS
 #define EFFT_COL_SETS 2
 #endif
+#ifndef EFFT_C64_COL_SETS
+#define EFFT_C64_COL_SETS 2
+#endif
+// Complex64 lines of 512 points: two sets of 32 lines (512-byte runs) at
+// large strides (1), or one set of 32 (0).  Measured on gfx950, 2^34
+// complex64 in place: first pass 79.1 -> 75.3 ms.
+#ifndef EFFT_C64_SETS9
+#define EFFT_C64_SETS9 1
+#endif
 inline int col_sets(int dtype_bytes, int logl, int lines, int64_t stride)
 {
-    return (EFFT_COL_SETS >= 2 && dtype_bytes == 16 && logl == 10 && lines == col_lines_max(dtype_bytes, logl) &&
-            lines * dtype_bytes == 128 && stride >= (int64_t(1) << 16))
-               ? 2
-               : 1;
+    if (lines != col_lines_max(dtype_bytes, logl) || stride < (int64_t(1) << 16)) return 1;
+    if (logl == 9 && dtype_bytes == 8) return EFFT_C64_SETS9 ? 2 : 1;
+    const int want = dtype_bytes == 16 ? EFFT_COL_SETS : EFFT_C64_COL_SETS;
+    return (want >= 2 && logl == 10 && lines * dtype_bytes == 128) ? 2 : 1;
 }
 
 // Non-temporal hints of a pass (measured on gfx950 at 2^30 points: they speed

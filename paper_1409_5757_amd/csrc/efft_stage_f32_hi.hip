@@ -1,0 +1,6 @@
+// efft_stage_f32_hi.hip -- sub-FFT pass kernels for complex64 lines of 512 .. 4096 points.
+#include "efft_stage.hpp"
+
+namespace efft {
+EFFT_STAGE_LAUNCHER(launch_stage_f32_hi, float, 9, 12)
+}  // namespace efft

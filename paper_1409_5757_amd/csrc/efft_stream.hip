@@ -5,7 +5,7 @@
 // Fig. "fig:parallel-perf").  The GPU counterpart is a plain streaming copy
 // with the access style of the transform's passes: 16-byte loads and stores
 // with the non-temporal hint, consecutive lanes on consecutive addresses,
-// four independent loads in flight per thread.  With dst == src it rewrites
+// many independent loads in flight per thread.  With dst == src it rewrites
 // the range in place, the pattern of an in-place pass.
 #include <hip/hip_runtime.h>
 
@@ -16,13 +16,23 @@ namespace efft {
 namespace {
 
 constexpr int BT = 256;
-constexpr int UNROLL = 4;  // measured on gfx950: 8 and 16 are 5-10% slower
 
+// One workgroup copies one contiguous chunk of BT * UNROLL 16-byte elements:
+// every thread issues all UNROLL loads (consecutive lanes on consecutive
+// addresses, one wave-wide 1 KiB run per load), then all UNROLL stores, the
+// access pattern of a contiguous-line pass, and the workgroup ends (the
+// hardware refills the CU with the next chunk).  The tail chunk is guarded.
+template <int UNROLL>
 __global__ void __launch_bounds__(BT) stream_copy_kernel(double2 *dst, const double2 *src, int64_t n)
 {
-    const int64_t step = int64_t(gridDim.x) * BT * UNROLL;
-    for (int64_t base = int64_t(blockIdx.x) * BT * UNROLL + threadIdx.x; base < n; base += step) {
-        double2 v[UNROLL];
+    const int64_t base = int64_t(blockIdx.x) * BT * UNROLL + threadIdx.x;
+    double2 v[UNROLL];
+    if (base + int64_t(BT) * (UNROLL - 1) < n) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) v[u] = load_nt(src + base + int64_t(u) * BT);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) store_nt(dst + base + int64_t(u) * BT, v[u]);
+    } else {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             const int64_t i = base + int64_t(u) * BT;
@@ -35,6 +45,18 @@ __global__ void __launch_bounds__(BT) stream_copy_kernel(double2 *dst, const dou
         }
     }
 }
+
+// 16 loads of 16 bytes in flight per thread (64 KiB per workgroup); measured
+// on gfx950 against 4 and 8 (see the benchmark's copy reference)
+#ifndef EFFT_COPY_UNROLL
+#define EFFT_COPY_UNROLL 16
+#endif
+constexpr int UNROLL = EFFT_COPY_UNROLL;
+// LDS reserved per workgroup (unused; it caps how many workgroups share a
+// CU, as the exchange buffers of the transform's passes do)
+#ifndef EFFT_COPY_LDS_KB
+#define EFFT_COPY_LDS_KB 0
+#endif
 
 }  // namespace
 }  // namespace efft
@@ -51,9 +73,10 @@ extern "C" int efft_stream_copy(void *dst, const void *src, int64_t bytes, void 
     if (bytes == 0) return EFFT_OK;
     const int64_t n = bytes / 16;
     const int64_t per_block = int64_t(efft::BT) * efft::UNROLL;
-    int64_t blocks = (n + per_block - 1) / per_block;
-    if (blocks > (int64_t(1) << 20)) blocks = int64_t(1) << 20;
-    hipLaunchKernelGGL(efft::stream_copy_kernel, dim3(unsigned(blocks)), dim3(efft::BT), 0,
+    const int64_t blocks = (n + per_block - 1) / per_block;
+    if (blocks > int64_t(0x7fffffff)) return EFFT_ERR_ARG;  // beyond one grid (> 128 TiB)
+    hipLaunchKernelGGL(efft::stream_copy_kernel<efft::UNROLL>, dim3(unsigned(blocks)), dim3(efft::BT),
+                       EFFT_COPY_LDS_KB * 1024,
                        static_cast<hipStream_t>(stream), static_cast<double2 *>(dst),
                        static_cast<const double2 *>(src), n);
     return hipGetLastError() == hipSuccess ? EFFT_OK : EFFT_ERR_HIP;

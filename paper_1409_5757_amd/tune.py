@@ -47,14 +47,15 @@ def key(n: int, dtype: torch.dtype, inplace: bool, batch: int = 1, scratch: bool
             f"{'scratch' if scratch else 'plain'}/{dev}")
 
 
-def decompositions(q: int, inplace: bool, max_digits: int = 4) -> list[list[int]]:
-    """Decompositions the strided kernels can run: digits in [4, 10] (or one
-    digit q <= 12), palindromic for in-place plans, at most max_digits."""
+def decompositions(q: int, inplace: bool, max_digits: int = 4, max_digit: int = 12) -> list[list[int]]:
+    """Decompositions the strided kernels can run: digits in [4, max_digit]
+    (at most 12; or one digit q <= 12), palindromic for in-place plans, at
+    most max_digits."""
     if q <= 12:
         return [[q]]
     out = []
     for m in range(2, max_digits + 1):
-        for d in itertools.product(range(4, 11), repeat=m):
+        for d in itertools.product(range(4, min(max_digit, 12) + 1), repeat=m):
             if sum(d) == q and (not inplace or d == d[::-1]):
                 out.append(list(d))
     # fewest passes first, then the most balanced (the planner's own preference)

@@ -143,6 +143,7 @@ def test_plan_digits_rejects_unusable_decompositions(lib):
     assert mk(1 << 20, 1, [8, 12]) is None and lib.efft_last_error() == -11      # not a palindrome
     assert mk(1 << 20, 0, [10, 9]) is None and lib.efft_last_error() == -11      # sum != q
     assert mk(1 << 20, 0, [3, 17]) is None and lib.efft_last_error() == -11      # digit out of range
+    assert mk(1 << 26, 0, [13, 13]) is None and lib.efft_last_error() == -11     # strided digit > 12
     assert mk(1 << 13, 0, [13]) is None and lib.efft_last_error() == -11         # one digit > 12
     assert mk(1 << 30, 1, [5, 5, 5, 5, 5, 5, 0]) is None and lib.efft_last_error() == -11  # too many
     assert lib.efft_plan_digits(1 << 20, 1, C128, -1, 1, 1.0, None, 2) is None
@@ -156,6 +157,8 @@ def test_tuner_decompositions():
     assert tune.decompositions(12, True) == [[12]]
     d30 = tune.decompositions(30, True)
     assert [10, 10, 10] in d30 and all(x == x[::-1] and sum(x) == 30 for x in d30)
-    assert all(4 <= v <= 10 for x in d30 for v in x)
+    assert all(4 <= v <= 12 for x in d30 for v in x) and [9, 12, 9] in d30
+    assert all(v <= 10 for x in tune.decompositions(30, True, max_digit=10) for v in x)
     d32 = tune.decompositions(32, False)
-    assert [8, 8, 8, 8] in d32 and [10, 10, 6, 6] in d32
+    assert [8, 8, 8, 8] in d32 and [10, 10, 6, 6] in d32 and [10, 12, 10] in d32
+    assert d32[0] == [10, 12, 10] or len(d32[0]) == 3

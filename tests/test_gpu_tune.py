@@ -59,15 +59,30 @@ def test_tune_and_wisdom_round_trip():
         assert tune._options(p, False, i) == opts
 
 
-def test_forced_decompositions_match_oracle():
-    for n, dtype, inplace, digits in [(1 << 20, torch.complex128, True, [5, 10, 5]),
-                                      (1 << 20, torch.complex128, False, [4, 8, 8]),
-                                      (1 << 24, torch.complex64, True, [6, 6, 6, 6]),
-                                      (1 << 24, torch.complex64, False, [10, 4, 10])]:
-        p = tune.make_plan(n, dtype, inplace, digits)
-        xh = host_input("uniform", 9, n, dtype)
+FORCED = [  # (n, dtype, in place, digits): balanced, unbalanced, and strided lines of 2^11 and 2^12 points
+    (1 << 20, torch.complex128, True, [5, 10, 5]), (1 << 20, torch.complex128, False, [4, 8, 8]),
+    (1 << 24, torch.complex64, True, [6, 6, 6, 6]), (1 << 24, torch.complex64, False, [10, 4, 10]),
+    (1 << 24, torch.complex64, False, [12, 6, 6]), (1 << 24, torch.complex128, True, [6, 12, 6]),
+    (1 << 22, torch.complex64, True, [5, 12, 5]), (1 << 23, torch.complex128, False, [11, 12]),
+    (1 << 24, torch.complex64, True, [12, 12]), (1 << 22, torch.complex128, True, [11, 11]),
+    (1 << 26, torch.complex64, False, [10, 12, 4]), (1 << 25, torch.complex128, False, [4, 11, 10]),
+]
+
+
+@pytest.mark.parametrize("n,dtype,inplace,digits", FORCED,
+                         ids=[f"2^{f[0].bit_length() - 1}-{'c128' if f[1] == torch.complex128 else 'c64'}-"
+                              f"{'ip' if f[2] else 'oop'}-{'.'.join(map(str, f[3]))}" for f in FORCED])
+def test_forced_decompositions_match_oracle(n, dtype, inplace, digits):
+    p = tune.make_plan(n, dtype, inplace, digits)
+    for direction, scratch in ((-1, False), (1, inplace)):
+        if direction == 1:
+            p.close()
+            p = tune.make_plan(n, dtype, inplace, digits, direction=1)
+        xh = host_input("uniform", 9 + direction, n, dtype)
         x = torch.from_numpy(xh).cuda()
-        y = p.execute(x)
-        err = rel_l2(y.cpu().numpy(), oracle.fft(xh))
-        print(f"n=2^{n.bit_length() - 1} digits={digits}: rel_l2={err:.2e}", flush=True)
+        y = p.execute(x, scratch=p.make_scratch() if scratch else None) if inplace else p.execute(x)
+        err = rel_l2(y.cpu().numpy(), oracle.fft(xh, direction))
+        print(f"n=2^{n.bit_length() - 1} digits={digits} dir={direction:+d} scratch={scratch}: rel_l2={err:.2e}",
+              flush=True)
         assert err <= TOL[dtype]
+    p.close()
