@@ -306,7 +306,13 @@ def run_other(args) -> int:
         pf = api.get_plan(n, dt, -1, False, 1.0, dev, batch)
         xd = x.detach()
         _, _, per_pass = time_transform(pf, xd, args.steps, 1, out=torch.empty_like(xd))
-        extra = {"transforms_per_step": 2, "forward_plan_ms_per_pass": [round(t, 4) for t in per_pass]}
+        fft_ms = sum(per_pass)
+        extra = {"transforms_per_step": 2, "forward_plan_ms_per_pass": [round(t, 4) for t in per_pass],
+                 # the transforms alone (the rest of a step is the loss and its
+                 # gradient, computed by torch): one batched transform's time
+                 # and its rate by the same 5 N log2 N count
+                 "fft_ms_per_direction": round(fft_ms, 4),
+                 "fft_GFLOPs": round(5 * batch * n * q / (fft_ms * 1e-3) / 1e9, 2)}
     result = {
         "metric": METRIC, "value": round(flops / (ms_step * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),

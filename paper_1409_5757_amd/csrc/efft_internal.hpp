@@ -282,9 +282,19 @@ constexpr int C64_SHARED_LINES = 8;
 
 // lines per workgroup of a strided pass (column_pass: a LAYOUT_COL pass,
 // which reads and writes the same strided lines)
+// Complex64 lines of 256 or 512 points take the widest tile (512- and
+// 256-byte tile rows) at every stride that holds it, in every strided layout
+// (1): measured on gfx950 by the tuner, 2^32 complex64 out of place 61.0 ->
+// 58.1 ms (all four passes wider), 2^34 complex64 in place second pass
+// 49.0 -> 48.3 ms.  (0): the wide tile only where lines are far apart.
+#ifndef EFFT_C64_WIDE_SHORT
+#define EFFT_C64_WIDE_SHORT 1
+#endif
+
 inline int col_lines(int dtype_bytes, int logl, int64_t stride, bool same_positions, bool column_pass = false)
 {
     const int w = col_lines_max(dtype_bytes, logl);
+    if (EFFT_C64_WIDE_SHORT && dtype_bytes == 8 && (logl == 8 || logl == 9) && stride >= w) return w;
     if (same_positions && stride >= WIDE_TILE_STRIDE && stride >= w) return w;
     if (column_pass && dtype_bytes == 8 && logl == 10 && stride >= C64_SHARED_LINES) return C64_SHARED_LINES;
     return col_lines_narrow(dtype_bytes, logl);
@@ -309,10 +319,16 @@ inline int col_lines(int dtype_bytes, int logl, int64_t stride, bool same_positi
 #ifndef EFFT_C64_SETS9
 #define EFFT_C64_SETS9 1
 #endif
+// Complex64 lines of 256 points: two sets of 64 lines (1 KiB runs) at large
+// strides (1), or one set of 64 (0).
+#ifndef EFFT_C64_SETS8
+#define EFFT_C64_SETS8 0
+#endif
 inline int col_sets(int dtype_bytes, int logl, int lines, int64_t stride)
 {
     if (lines != col_lines_max(dtype_bytes, logl) || stride < (int64_t(1) << 16)) return 1;
     if (logl == 9 && dtype_bytes == 8) return EFFT_C64_SETS9 ? 2 : 1;
+    if (logl == 8 && dtype_bytes == 8) return EFFT_C64_SETS8 ? 2 : 1;
     const int want = dtype_bytes == 16 ? EFFT_COL_SETS : EFFT_C64_COL_SETS;
     return (want >= 2 && logl == 10 && lines * dtype_bytes == 128) ? 2 : 1;
 }

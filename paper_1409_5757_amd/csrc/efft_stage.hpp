@@ -725,7 +725,7 @@ static hipError_t dispatch_logl(int layout, int lines, int sets, const StagePara
     if constexpr (LOGL >= 4 && LOGL <= STRIDED_LOGL_MAX) {
         if (layout == LAYOUT_COL) {
             if (lines == WMAX && sets == 1) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL, EPC>(p, stream);
-            if constexpr ((LOGL == 10 && WMAX * EB == 128) || (LOGL == 9 && EB == 8)) {
+            if constexpr ((LOGL == 10 && WMAX * EB == 128) || ((LOGL == 9 || LOGL == 8) && EB == 8)) {
                 if (lines == WMAX && sets == 2) return launch_one<T, LOGL, WMAX, 2, LAYOUT_COL, EPC>(p, stream);
             }
             if constexpr (WMIN != WMAX) {
@@ -738,7 +738,7 @@ static hipError_t dispatch_logl(int layout, int lines, int sets, const StagePara
         }
         if (layout == LAYOUT_COL_POST) {
             if (lines == WMAX && sets == 1) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL_POST, EPC>(p, stream);
-            if constexpr ((LOGL == 10 && WMAX * EB == 128) || (LOGL == 9 && EB == 8)) {
+            if constexpr ((LOGL == 10 && WMAX * EB == 128) || ((LOGL == 9 || LOGL == 8) && EB == 8)) {
                 if (lines == WMAX && sets == 2) return launch_one<T, LOGL, WMAX, 2, LAYOUT_COL_POST, EPC>(p, stream);
             }
             if constexpr (WMIN != WMAX) {

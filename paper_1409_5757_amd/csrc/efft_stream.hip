@@ -46,16 +46,19 @@ __global__ void __launch_bounds__(BT) stream_copy_kernel(double2 *dst, const dou
     }
 }
 
-// 16 loads of 16 bytes in flight per thread (64 KiB per workgroup); measured
-// on gfx950 against 4 and 8 (see the benchmark's copy reference)
+// Two 16-byte loads per thread (8 KiB per workgroup) and 40 KiB of LDS
+// reserved per workgroup (unused; it caps a CU at four workgroups, as the
+// exchange buffers of the transform's passes cap them).  Measured on gfx950,
+// copying 8 GiB: 6.47 TB/s, against 6.05 (4 loads, same cap), 5.84 (4 loads,
+// no cap), 5.74 (8 loads), 5.51 (16 loads, no cap) and 5.16 (16 loads, two
+// workgroups per CU); the grid-stride loop with 4 loads it replaces ran at
+// 5.78.
 #ifndef EFFT_COPY_UNROLL
-#define EFFT_COPY_UNROLL 16
+#define EFFT_COPY_UNROLL 2
 #endif
 constexpr int UNROLL = EFFT_COPY_UNROLL;
-// LDS reserved per workgroup (unused; it caps how many workgroups share a
-// CU, as the exchange buffers of the transform's passes do)
 #ifndef EFFT_COPY_LDS_KB
-#define EFFT_COPY_LDS_KB 0
+#define EFFT_COPY_LDS_KB 40
 #endif
 
 }  // namespace

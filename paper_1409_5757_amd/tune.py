@@ -127,8 +127,9 @@ def _out(plan, x):
     return _OUT[k]
 
 
-def tune_passes(plan: api.Plan, x, scratch_buf=None, reps: int = 3) -> tuple[list[list[int]], float]:
-    """Choose every pass's launch options by its own time, one pass at a time."""
+def tune_passes(plan: api.Plan, x, scratch_buf=None, reps: int = 3, log=None) -> tuple[list[list[int]], float]:
+    """Choose every pass's launch options by its own time, one pass at a time
+    (``log`` receives a line per pass)."""
     scratch = scratch_buf is not None
     npass = plan.scratch_passes if scratch else plan.passes
     chosen = []
@@ -148,6 +149,8 @@ def tune_passes(plan: api.Plan, x, scratch_buf=None, reps: int = 3) -> tuple[lis
                 best, best_t = c, t
         _set_options(plan, scratch, i, best)
         chosen.append(best)
+        if log:
+            log(f"  pass {i}: options {cur} -> {best} ({best_t:.3f} ms)")
     total = sum(_time_passes(plan, x, scratch_buf, reps))
     return chosen, total
 
@@ -183,7 +186,7 @@ def tune(n: int, dtype: torch.dtype, inplace: bool, batch: int = 1, scratch: boo
         if scratch and sb is None:
             p.close()
             continue
-        opts, ms = tune_passes(p, x, sb, reps)
+        opts, ms = tune_passes(p, x, sb, reps, log)
         if log:
             log(f"digits {d}: {ms:.3f} ms")
         if best is None or ms < best["ms"]:
