@@ -32,6 +32,28 @@ namespace efft {
 // recomputes what depends on it instead of keeping an earlier result alive
 // in registers (an empty asm statement; no instruction is emitted).
 template <typename X> __device__ __forceinline__ void opaque(X &x) { asm volatile("" : "+v"(x)); }
+// Whether a pass kernel holds the wave-uniform addressing form of its strided
+// loads and stores: complex128 passes never take it (the host keeps off32
+// clear for them) unless EFFT_WAVE_UNIFORM_C128 is set, and leaving the code
+// out of their kernels saves its address arithmetic.
+template <typename V> constexpr bool uniform_code()
+{
+    return sizeof(decltype(V{}.x)) == 4 || EFFT_WAVE_UNIFORM_C128;
+}
+
+// The recomputation barriers (opaque copies) below keep the complex64 tiles
+// of two line sets within their registers; complex128 kernels have the room
+// and run faster without them (measured on gfx950, 2^30 complex128 in place,
+// first pass: 8.13 -> 7.88 ms).
+#ifndef EFFT_OPAQUE_C128
+#define EFFT_OPAQUE_C128 0
+#endif
+
+// opaque() where the element type asks for it
+template <typename V, typename X> __device__ __forceinline__ void opaque_for(X &x)
+{
+    if constexpr (sizeof(decltype(V{}.x)) == 4 || EFFT_OPAQUE_C128) opaque(x);
+}
 
 // LDS index of point p of a line: one padding slot per 16 points breaks the
 // power-of-two strides of the Stockham writes across banks
@@ -132,7 +154,7 @@ __device__ __forceinline__ void stockham_step(V *v, V *lds_line, int t, const Tw
             for (int r = 1; r < R; ++r) u[r] = cmul(u[r], ltw[(jm * r * (L / (NS * R))) & (L - 1)]);
         } else if constexpr (NS > 1) {
             int jm = j & (NS - 1);
-            opaque(jm);
+            opaque_for<V>(jm);
             // W_{NS*R}^{jm} = W_N^{jm * N/(NS*R)}
             const uint64_t m = uint64_t(jm) * (n_over_l * uint64_t(L / (NS * R)));
             twiddle_line<V, R>(u, tw_lookup(tt, m));
@@ -158,10 +180,45 @@ __device__ __forceinline__ void lds_gather(V *v, const V *lds_line, int t)
     for (int i = 0; i < E; ++i) v[i] = lds_line[lds_pad(t + P * i)];
 }
 
+// The exchange between two Stockham steps done one component at a time
+// through a line buffer of real numbers (half the LDS of a complex one): on
+// entry v holds the step's outputs in registers (output r of butterfly b in
+// register b + (E/R)*r, line position (j/NS)*NS*R + (j mod NS) + NS*r); on
+// exit v holds points t + P*i.  The real parts are written, gathered, then the
+// imaginary parts: each gather overwrites only the component already written.
+template <typename V, int L, int R, int NS, int EP>
+__device__ __forceinline__ void exchange_split(V *v, decltype(V{}.x) *lds_line, int t)
+{
+    constexpr int E = LineGeom<L, EP>::E;
+    constexpr int P = LineGeom<L, EP>::P;
+    constexpr int NB = E / R;
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = t + P * b;
+            const int base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                lds_line[lds_pad(base + NS * r)] = comp ? v[b + NB * r].y : v[b + NB * r].x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const auto w = lds_line[lds_pad(t + P * i)];
+            if (comp)
+                v[i].y = w;
+            else
+                v[i].x = w;
+        }
+        __syncthreads();
+    }
+}
+
 // All Stockham steps of a line of 2^LOGL points.  On entry v holds input
 // points t + P*i; on exit outputs k = t + P*i (FINAL_TO_LDS: the outputs are
 // left in LDS at natural positions instead).
-template <typename V, int LOGL, bool FINAL_TO_LDS, int EP, bool TWL = false>
+template <typename V, int LOGL, bool FINAL_TO_LDS, int EP, bool TWL = false, bool SPLIT = false>
 __device__ __forceinline__ void line_fft(V *v, V *lds_line, int t, const TwTable &tt,
                                          uint64_t n_over_l, const V *ltw = nullptr)
 {
@@ -169,6 +226,25 @@ __device__ __forceinline__ void line_fft(V *v, V *lds_line, int t, const TwTable
     using Rd = Radices<LOGL>;
     constexpr int NST = Rd::NSTEPS;
     static_assert(NST <= 4, "line too long");
+    if constexpr (SPLIT) {
+        // lds_line is a line of PADDED real numbers
+        static_assert(!FINAL_TO_LDS && NST >= 2, "component exchange between steps, outputs in registers");
+        using T = decltype(V{}.x);
+        T *ll = reinterpret_cast<T *>(lds_line);
+        stockham_step<V, L, Rd::radix(0), 1, false, EP, TWL>(v, nullptr, t, tt, n_over_l, ltw);
+        exchange_split<V, L, Rd::radix(0), 1, EP>(v, ll, t);
+        if constexpr (NST >= 3) {
+            stockham_step<V, L, Rd::radix(1), Rd::span(1), false, EP, TWL>(v, nullptr, t, tt, n_over_l, ltw);
+            exchange_split<V, L, Rd::radix(1), Rd::span(1), EP>(v, ll, t);
+        }
+        if constexpr (NST >= 4) {
+            stockham_step<V, L, Rd::radix(2), Rd::span(2), false, EP, TWL>(v, nullptr, t, tt, n_over_l, ltw);
+            exchange_split<V, L, Rd::radix(2), Rd::span(2), EP>(v, ll, t);
+        }
+        stockham_step<V, L, Rd::radix(NST - 1), Rd::span(NST - 1), false, EP, TWL>(v, nullptr, t, tt, n_over_l,
+                                                                                    ltw);
+        return;
+    }
     // step 0
     if constexpr (NST == 1) {
         stockham_step<V, L, Rd::radix(0), 1, FINAL_TO_LDS, EP, TWL>(v, lds_line, t, tt, n_over_l, ltw);
@@ -207,7 +283,7 @@ __device__ __forceinline__ void apply_stage_twiddle(V *v, int t, uint64_t g, uin
                                                     const TwTable &tt)
 {
     const uint64_t gs = g * scale;
-    opaque(t);
+    opaque_for<V>(t);
     const double2 w0 = tw_lookup(tt, gs * uint64_t(t));
     const double2 s1 = tw_lookup(tt, gs * uint64_t(P));
     if constexpr (E == 1) {
@@ -451,6 +527,32 @@ __device__ __forceinline__ void store_points(V *p, int64_t stride, const V *w, i
 }
 
 // Transform the loaded tile and store it (the layout decides where).
+// Whether a pass kernel exchanges lines between Stockham steps one component
+// at a time (exchange_split): its LDS buffer is then half as large, so two
+// workgroups can share a CU where the registers allow it.
+// Measured on gfx950 (2^30 complex128 in place): the stride-2^10 pass of
+// single-set tiles, two workgroups per CU instead of one, 6.67 -> 6.24 ms;
+// the first pass is held to one workgroup per CU by the registers of its two
+// line sets and does not gain, nor do the row passes (4 -> 8 workgroups per
+// CU: 5.44 -> 5.68 ms) or complex64 (its tiles already share CUs).
+#ifndef EFFT_SPLIT_C128
+#define EFFT_SPLIT_C128 1
+#endif
+#ifndef EFFT_SPLIT_C64
+#define EFFT_SPLIT_C64 0
+#endif
+template <typename V, int LOGL, int SETS, int LAYOUT> constexpr bool split_exchange()
+{
+    if (Radices<LOGL>::NSTEPS < 2) return false;
+    const bool col = LAYOUT == LAYOUT_COL || LAYOUT == LAYOUT_COL_POST;
+    if (!col && LAYOUT != LAYOUT_ROW) return false;
+    const int mode = sizeof(decltype(V{}.x)) == 8 ? EFFT_SPLIT_C128 : EFFT_SPLIT_C64;
+    // 1: single-set strided passes; 2: also every-set strided passes; 3: also row passes
+    if (mode == 1) return col && SETS == 1;
+    if (mode == 2) return col;
+    return mode >= 3;
+}
+
 template <typename V, int LOGL, int LINES, int SETS, int LAYOUT, int EP, bool TWL, int E>
 __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SETS> &a, V *lds, V *dst,
                                              int c, int t, int tid, const StageParams &sp, int64_t t0,
@@ -499,9 +601,12 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
             // copies): keeping the first set's for the second costs more
             // registers than recomputing them
             int tl = t, cl = c;
-            opaque(tl);
-            opaque(cl);
-            line_fft<V, LOGL, false, EP, TWL>(v[st], lds + cl * PADDED, tl, sp.tt, sp.n_over_l, ltw);
+            opaque_for<V>(tl);
+            opaque_for<V>(cl);
+            constexpr bool SPLIT = split_exchange<V, LOGL, SETS, LAYOUT>();
+            using T = decltype(V{}.x);
+            V *my_line = SPLIT ? reinterpret_cast<V *>(reinterpret_cast<T *>(lds) + cl * PADDED) : lds + cl * PADDED;
+            line_fft<V, LOGL, false, EP, TWL, SPLIT>(v[st], my_line, tl, sp.tt, sp.n_over_l, ltw);
             if (sp.twmode != TW_NONE) {
                 const uint64_t g = sp.twmode == TW_OFFSET ? uint64_t(a.off[st])
                                                           : digit_reverse(uint64_t(a.blk[st]), sp.rev);
@@ -512,7 +617,7 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
                 store_post<V, E>(v[st], a.base[st] + sp.s * int64_t(t), sp.s * int64_t(P), sp);
             else if constexpr (SETS == 1 || !EFFT_SETS_STORE_TOGETHER)
             {
-                if (sp.off32) {
+                if (uniform_code<V>() && sp.off32) {
 #pragma unroll
                     for (int i = 0; i < E; ++i)
                         store_g(at_offset(wave_uniform(dst + (a.ubase[st] + sp.s * (t0 + int64_t(P) * i))), loff),
@@ -587,13 +692,16 @@ __global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()))
     static_assert((LAYOUT != LAYOUT_COL2ROW && LAYOUT != LAYOUT_COL2ROW_PRE) || SETS == 1,
                   "one line set for row writes");
     static_assert(LAYOUT != LAYOUT_ROW2COL || SETS == 1, "one line set for column writes");
-    __shared__ V lds[NEED_LDS ? LINES * PADDED : PADDED];
+    constexpr bool SPLIT = split_exchange<V, LOGL, SETS, LAYOUT>();
+    // the exchange buffer: LINES lines of complex numbers, or of real numbers
+    // for the component-wise exchange (viewed through V * all the same)
+    __shared__ V lds[NEED_LDS ? (SPLIT ? (LINES * PADDED + 1) / 2 : LINES * PADDED) : PADDED];
     // complex64: the in-line twiddles W_L^e of every Stockham step come from
     // a table of the line length in LDS, filled from the plan's FP32 table of
     // W_4096^e (computed in FP64, rounded once) -- no FP64 work per twiddle;
     // where the LDS has no room for it (2^12-point strided lines) they are
     // generated in FP64 as for complex128
-    constexpr int LDS_EXCH = int(sizeof(V)) * (NEED_LDS ? LINES * PADDED : PADDED);
+    constexpr int LDS_EXCH = int(sizeof(V)) * (NEED_LDS ? (SPLIT ? (LINES * PADDED + 1) / 2 : LINES * PADDED) : PADDED);
     constexpr bool TWL = EFFT_C64_LDS_TW && sizeof(T) == 4 && Radices<LOGL>::NSTEPS > 1 &&
                          LDS_EXCH + L * int(sizeof(V)) <= 163840;
     __shared__ V ltw[TWL ? L : 1];
@@ -616,8 +724,9 @@ __global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()))
     V *dst = static_cast<V *>(sp.dst);
     // strided layouts: the wave's first t and the lane's byte offset from it
     // (c + s * (t - t0) elements; meaningful when sp.off32 is set)
-    const int64_t t0 = (int64_t(__builtin_amdgcn_readfirstlane(tid >> 6)) * 64) / LINES;
-    const uint32_t loff = uint32_t((int64_t(c) + sp.s * (int64_t(t) - t0)) * int64_t(sizeof(V)));
+    constexpr bool UNIFORM = uniform_code<V>();
+    const int64_t t0 = UNIFORM ? (int64_t(__builtin_amdgcn_readfirstlane(tid >> 6)) * 64) / LINES : 0;
+    const uint32_t loff = UNIFORM ? uint32_t((int64_t(c) + sp.s * (int64_t(t) - t0)) * int64_t(sizeof(V))) : 0;
 
     // virtual workgroup number of this workgroup's it-th tile: the PIPE tiles
     // of a workgroup stay on its XCD's run when the grid allows
@@ -635,7 +744,7 @@ __global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()))
         if constexpr (LAYOUT == LAYOUT_COL2ROW_PRE)
             load_tile_pre<V, E, P, SETS>(dst_v, at, src, t, sp);
         else if constexpr (LAYOUT == LAYOUT_COL || LAYOUT == LAYOUT_COL_POST || LAYOUT == LAYOUT_COL2ROW) {
-            if (sp.off32)
+            if (UNIFORM && sp.off32)
                 load_tile_uniform<V, E, P, SETS>(dst_v, at, src, sp.s, t0, loff, sp.nt_load);
             else
                 load_tile<V, E, P, SETS>(dst_v, at, src, t, sp.s, sp.nt_load);

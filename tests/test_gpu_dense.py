@@ -21,6 +21,15 @@ Which plan shape each size reaches (digits log2, planner's choice):
   stride (the 2^34 first pass).
 * 2^25 complex64 out of place, (9, 8, 8): 64 lines of 256 points at a 2^17
   stride (the slowest 2^32 out-of-place pass, and the 2^34 second pass).
+* 2^25 complex128 out of place, (9, 8, 8): the transposing first pass of
+  512-point lines, two tiles per workgroup with the second tile's loads in
+  flight while the first is transformed, and the stride-2^8 middle pass of
+  single-set tiles with the component-wise LDS exchange.
+
+Every plan above, and the out-of-place 2^26 and 2^27 complex128 plans, must
+also give bitwise the same output when run twice on the same input: a result
+that changes from run to run (a race, a register read before its load has
+landed) shows up there even where it stays within the tolerance.
 
 The full 2^30 complex128 in-place spectrum of the benchmark's own plan is
 compared on every bin too when the host has the memory for three 16 GiB
@@ -45,6 +54,7 @@ CASES = [  # (log2 N, dtype, in place, digits the planner must choose)
     (28, C64, True, [10, 8, 10]),
     (26, C64, True, [9, 8, 9]),
     (25, C64, False, [9, 8, 8]),
+    (25, C128, False, [9, 8, 8]),
 ]
 
 
@@ -163,3 +173,32 @@ def test_c2_2p30_complex128_in_place_dense():
     del x
     torch.cuda.empty_cache()
 
+
+
+REPEAT_CASES = [(q, dt, ip) for q, dt, ip, _ in CASES] + [(26, C128, False), (27, C128, False)]
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("q,dtype,inplace", REPEAT_CASES,
+                         ids=[f"2^{c[0]}-{'c128' if c[1] == C128 else 'c64'}-{'inplace' if c[2] else 'oop'}"
+                              for c in REPEAT_CASES])
+def test_dense_run_twice_bitwise(q, dtype, inplace):
+    n = 1 << q
+    torch.cuda.empty_cache()
+    x = torch.empty(n, dtype=dtype, device=DEV)
+    inputs.fill_uniform_torch(x, seed=300 + q)
+    plan = api.get_plan(n, dtype, -1, inplace, 1.0, DEV)
+    outs = []
+    for _ in range(2):
+        if inplace:
+            y = x.clone()
+            plan.execute(y)
+        else:
+            y = torch.full_like(x, float("nan"))
+            plan.execute(x, out=y)
+        outs.append(y)
+    torch.cuda.synchronize()
+    assert not bool(torch.isnan(outs[0]).any()), "an output element was not written"
+    assert torch.equal(outs[0], outs[1]), "two runs of the same plan on the same input differ"
+    del x, outs
+    torch.cuda.empty_cache()
