@@ -8,10 +8,13 @@ Reports GFLOP/s = 5 N log2 N / t (the nominal complex-FFT count; the paper's
 Eq. "eqflops" is the real-input half of it), per-pass HBM bandwidth from HIP
 events recorded on the launch stream inside the timed region, the same
 transform in complex64 for the FP32 speedup and its error against the FP64
-path, the paper's own real-input FP32 transform at the same N, a device-copy
-ceiling, and the FP64 CPU oracle timed on a bounded sample on the host cores.
+path, the paper's own real-input FP32 transform at the same N, the other
+workloads (2^20 complex128 out of place, 2^32 complex64 out of place, 2^34
+complex64 forward + inverse in place, 64 x 2^24 complex64 through autograd)
+under "other_workloads", a device-copy ceiling, and the FP64 CPU oracle timed
+on a bounded sample on the host cores.
 
-    python bench.py [--steps K] [--warmup W] [--log2n Q] [--no-fp32] [--no-real] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--log2n Q] [--no-fp32] [--no-real] [--no-cpu] [--no-others]
     python bench.py --workload c1|c3|c4|c5    # the other workloads, one line each:
         c1 2^20 complex128 out of place; c3 2^32 complex64 out of place;
         c4 2^34 complex64 in place, forward + inverse; c5 64 x 2^24 complex64
@@ -206,11 +209,23 @@ def roofline(per_pass, bytes_pass):
 
 
 def run_other(args) -> int:
-    """One JSON line for workload c1, c3, c4 or c5 (same keys as the default
-    line; per-pass times from the library's events on the launch stream)."""
+    """One JSON line for workload c1, c2f32, c3, c4 or c5 (same keys as the
+    default line)."""
+    result = measure_other(args.workload, args.steps, args.warmup)
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def measure_other(workload: str, steps: int, warmup: int) -> dict:
+    """Measure workload c1, c2f32, c3, c4 or c5 (per-pass times from the
+    library's events on the launch stream); the arrays are freed on return."""
+    import types
     import torch
     from paper_1409_5757_amd import _lib, api, inputs
 
+    args = types.SimpleNamespace(workload=workload, steps=steps, warmup=warmup)
     _lib.load()
     label, q, dtn, inplace, batch = OTHER_WORKLOADS[args.workload]
     dt = getattr(torch, dtn)
@@ -325,10 +340,26 @@ def run_other(args) -> int:
                           for i, t in enumerate(per_pass)],
         **extra,
     }
-    if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(result), flush=True)
-    return 0
+    del x
+    torch.cuda.empty_cache()
+    return result
+
+
+# The other workloads measured by the default run, with their step counts
+# (steps, warmup), so that one run of bench.py reports every workload.
+COMPANIONS = {"c1": (10, 3), "c3": (5, 1), "c4": (2, 1), "c5": (3, 1)}
+
+
+def companion(r: dict) -> dict:
+    """The part of a workload's line that the default line carries."""
+    keep = ("value", "unit", "ms_per_step", "steps", "warmup", "dtype", "graph_replay", "forward_ms",
+            "inverse_ms", "fft_ms_per_direction", "fft_GFLOPs")
+    out = {"workload": r["config"]["workload"], "digits_log2": r["config"]["digits_log2"]}
+    out.update({k: r[k] for k in keep if k in r})
+    rf = r["roofline"]
+    out["dominant_pass"] = {"pass": rf["kernel_pass"], "GBps": rf["achieved"], "frac_of_hbm_peak": rf["frac"]}
+    out["ms_per_pass"] = [p["ms"] for p in r["passes_detail"]]
+    return out
 
 
 def main() -> int:
@@ -341,6 +372,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-real", action="store_true")
     ap.add_argument("--no-anylen", action="store_true")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the other workloads (c1, c3, c4, c5) that the default run also measures")
     ap.add_argument("--workload", choices=sorted(OTHER_WORKLOADS) + ["c2"], default="c2",
                     help="c2 (default): the in-place 2^30 complex128 transform with its companions; "
                          "c1, c3, c4, c5, c2f32: the other workloads, one JSON line each")
@@ -486,6 +519,10 @@ def main() -> int:
             del xa
             pa.close()
             torch.cuda.empty_cache()
+
+    if not args.no_others:
+        result["other_workloads"] = {name: companion(measure_other(name, st, wu))
+                                     for name, (st, wu) in COMPANIONS.items()}
 
     stream_gbps, torch_gbps = copy_ceiling(min(8 << 30, n * 16))
     result["copy_ceiling_GBps"] = round(stream_gbps, 1)  # efft_stream_copy

@@ -228,13 +228,13 @@ void apply_scale_to_last(std::vector<Pass> &v, double scale)
     }
 }
 
-void set_hints(std::vector<Pass> &v)
+void set_hints(std::vector<Pass> &v, int eb)
 {
     for (Pass &ps : v) {
         if (ps.swap)
             ps.wp.nt_hint = EFFT_NT_SWAP;
         else
-            set_stream_hints(ps.sp, ps.layout);
+            set_stream_hints(ps.sp, ps.layout, ps.lines * ps.sets, eb);
     }
 }
 
@@ -252,8 +252,8 @@ void build_passes(efft_plan_s *p, const TwTable &tt)
         build_scratch_passes(p, tt);
         apply_scale_to_last(p->scratch_passes, p->scale);
     }
-    set_hints(p->passes);
-    set_hints(p->scratch_passes);
+    set_hints(p->passes, p->eb);
+    set_hints(p->scratch_passes, p->eb);
     // a batch of contiguous signals: every sub-FFT pass's lines simply
     // continue into the next signal (blocks of the same structure), so only
     // the tile count grows; the swap runs one grid layer per signal
