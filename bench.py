@@ -208,6 +208,10 @@ def roofline(per_pass, bytes_pass):
             "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "kernel_pass": dom}
 
 
+# records of profiles/traffic.json taken on the other workloads' passes
+TRAFFIC_KEYS = {"c2f32": "c64_inplace_fwd_q30", "c3": "c64_oop_fwd_q32", "c4": "c64_inplace_fwd_inv_q34"}
+
+
 def run_other(args) -> int:
     """One JSON line for workload c1, c2f32, c3, c4 or c5 (same keys as the
     default line)."""
@@ -340,6 +344,8 @@ def measure_other(workload: str, steps: int, warmup: int) -> dict:
                           for i, t in enumerate(per_pass)],
         **extra,
     }
+    if workload in TRAFFIC_KEYS:
+        result["roofline"]["traffic"] = traffic_record(TRAFFIC_KEYS[workload], result["roofline"]["kernel_pass"])
     del x
     torch.cuda.empty_cache()
     return result
