@@ -1,12 +1,13 @@
 // efft_stream.hip -- the memory-bandwidth reference of the benchmark.
 //
-// The paper sets EFFT beside the STREAM benchmark to judge how well a
+// The paper sets EFFT beside the STREAM benchmark to assess how well a
 // bandwidth-bound transform uses the memory system (Section 5.4,
 // Fig. "fig:parallel-perf").  The GPU counterpart is a plain streaming copy
 // with the access style of the transform's passes: 16-byte loads and stores
 // with the non-temporal hint, consecutive lanes on consecutive addresses,
-// many independent loads in flight per thread.  With dst == src it rewrites
-// the range in place, the pattern of an in-place pass.
+// each workgroup loading its whole chunk before storing it, and as many
+// workgroups per CU as the passes have.  With dst == src it rewrites the
+// range in place, the pattern of an in-place pass.
 #include <hip/hip_runtime.h>
 
 #include "../../include/efft.h"
