@@ -541,9 +541,18 @@ __device__ __forceinline__ void store_points(V *p, int64_t stride, const V *w, i
 #ifndef EFFT_SPLIT_C64
 #define EFFT_SPLIT_C64 0
 #endif
+// The rows-to-columns pass (LAYOUT_ROW2COL) of complex128: its final
+// transpose through LDS goes one component at a time too, and it then runs
+// one tile per workgroup instead of two in turn, so two workgroups share a CU
+// (measured on gfx950, the last pass of the 2^30 scratch schedule: 7.99 ->
+// 6.63 ms).
+#ifndef EFFT_SPLIT_R2C
+#define EFFT_SPLIT_R2C 1
+#endif
 template <typename V, int LOGL, int SETS, int LAYOUT> constexpr bool split_exchange()
 {
     if (Radices<LOGL>::NSTEPS < 2) return false;
+    if (LAYOUT == LAYOUT_ROW2COL) return sizeof(decltype(V{}.x)) == 8 && EFFT_SPLIT_R2C && SETS == 1;
     const bool col = LAYOUT == LAYOUT_COL || LAYOUT == LAYOUT_COL_POST;
     if (!col && LAYOUT != LAYOUT_ROW) return false;
     const int mode = sizeof(decltype(V{}.x)) == 8 ? EFFT_SPLIT_C128 : EFFT_SPLIT_C64;
@@ -574,10 +583,39 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
         // outputs land in LDS in natural order; re-read them across the tile's
         // lines (lane = line) and write output k of column `line` at
         // line + row_mul * k, so each store covers LINES consecutive elements
-        line_fft<V, LOGL, true, EP, TWL>(v[0], lds_line, t, sp.tt, sp.n_over_l, ltw);
-        __syncthreads();
+        constexpr bool SPLIT = split_exchange<V, LOGL, SETS, LAYOUT>();
         const int c2 = tid % LINES;
         const int t2 = tid / LINES;
+        if constexpr (SPLIT) {
+            // outputs k = t + P*i stay in registers; the transpose goes
+            // through a buffer of real numbers, the real parts first, each
+            // read overwriting only the component already written
+            using T = decltype(V{}.x);
+            T *lt = reinterpret_cast<T *>(lds);
+            line_fft<V, LOGL, false, EP, TWL, true>(v[0], reinterpret_cast<V *>(lt + c * PADDED), t, sp.tt,
+                                                    sp.n_over_l, ltw);
+#pragma unroll
+            for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+                for (int i = 0; i < E; ++i) lt[c * PADDED + lds_pad(t + P * i)] = comp ? v[0][i].y : v[0][i].x;
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    const T x = lt[c2 * PADDED + lds_pad(t2 + P * i)];
+                    if (comp)
+                        v[0][i].y = x;
+                    else
+                        v[0][i].x = x;
+                }
+                __syncthreads();
+            }
+        } else {
+            line_fft<V, LOGL, true, EP, TWL>(v[0], lds_line, t, sp.tt, sp.n_over_l, ltw);
+            __syncthreads();
+            const V *col_lds = lds + c2 * PADDED;
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[0][i] = col_lds[lds_pad(t2 + P * i)];
+        }
         const int64_t cols = sp.row_mul;
         const int64_t line = a.tile * LINES + c2;
         int64_t col = (line & ~(cols - 1)) * L + (line & (cols - 1));  // signal * N + column
@@ -587,12 +625,8 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
             const int64_t g = line / ostride;
             col = g * ostride * L + (line - g * ostride);
         }
-        const V *col_lds = lds + c2 * PADDED;
-        V w[E];
-#pragma unroll
-        for (int i = 0; i < E; ++i) w[i] = col_lds[lds_pad(t2 + P * i)];
-        finish_outputs<V, E>(w, sp);
-        store_points<V, E>(dst + col + ostride * int64_t(t2), ostride * int64_t(P), w, sp.nt_store);
+        finish_outputs<V, E>(v[0], sp);
+        store_points<V, E>(dst + col + ostride * int64_t(t2), ostride * int64_t(P), v[0], sp.nt_store);
     } else if constexpr (LAYOUT != LAYOUT_COL2ROW && LAYOUT != LAYOUT_COL2ROW_PRE) {
 #pragma unroll
         for (int st = 0; st < SETS; ++st) {
@@ -806,7 +840,10 @@ static hipError_t launch_one(const StageParams &p, hipStream_t stream)
 {
     // a second tile in flight costs one more tile of registers: only
     // workgroups of at most 512 threads at 16 points per thread have room
-    constexpr bool ROOM = SETS == 1 && EP == 16 && LINES * LineGeom<(1 << LOGL), EP>::P <= 512;
+    // (not where the exchange goes one component at a time: its smaller LDS
+    // buffer lets two workgroups share a CU instead)
+    constexpr bool ROOM = SETS == 1 && EP == 16 && LINES * LineGeom<(1 << LOGL), EP>::P <= 512 &&
+                          !split_exchange<typename vec2<T>::type, LOGL, SETS, LAYOUT>();
     constexpr int PIPE = !ROOM ? 1
                          : (LAYOUT == LAYOUT_COL || LAYOUT == LAYOUT_COL_POST) ? EFFT_PIPE_COL
                          : (LAYOUT == LAYOUT_ROW) ? EFFT_PIPE_ROW : EFFT_PIPE_X;
