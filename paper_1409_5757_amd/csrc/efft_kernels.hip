@@ -3,6 +3,8 @@
 // in efft_stage.hpp (instantiated by efft_stage_*.hip).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "efft_internal.hpp"
 #include "efft_stage.hpp"
 
@@ -14,13 +16,19 @@ namespace efft {
 // Each unordered pair is handled by the workgroup whose key is the smaller;
 // a tile paired with itself is transposed in place.  Every element is read
 // and written exactly once.
-template <typename T, int TS, int NT, bool STREAM>
+//
+// SPLIT: both tiles are loaded into registers and transposed through LDS one
+// component at a time (real parts, then imaginary parts; each read overwrites
+// only the component already written), so the LDS holds real numbers, half
+// the bytes, and twice as many workgroups share a CU.
+template <typename T, int TS, int NT, bool STREAM, bool SPLIT>
 __global__ void __launch_bounds__(NT) swap_kernel(SwapParams p)
 {
     using V = typename vec2<T>::type;
     constexpr int ROWS_PER_PASS = NT / TS;
-    __shared__ V ta[TS][TS + 1];
-    __shared__ V tb[TS][TS + 1];
+    using E = typename std::conditional<SPLIT, T, V>::type;
+    __shared__ E ta[TS][TS + 1];
+    __shared__ E tb[TS][TS + 1];
 
     // grid: x = middle index mu (up to 2^24), y = tile pair I*nt + J (up to 1024)
     const int64_t mu = order_tiles(blockIdx.x, p.M, TILE_XCD);
@@ -48,6 +56,54 @@ __global__ void __launch_bounds__(NT) swap_kernel(SwapParams p)
         if constexpr (STREAM) store_nt(x + i, v);
         else x[i] = v;
     };
+    if constexpr (SPLIT) {
+        constexpr int K = TS / ROWS_PER_PASS;
+        V ra[K], rb[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) ra[k] = ld(baseA + (r0 + k * ROWS_PER_PASS) * rowA + col);
+        if (!self) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) rb[k] = ld(baseB + (r0 + k * ROWS_PER_PASS) * rowA + col);
+        }
+#pragma unroll
+        for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                ta[r0 + k * ROWS_PER_PASS][col] = comp ? ra[k].y : ra[k].x;
+                if (!self) tb[r0 + k * ROWS_PER_PASS][col] = comp ? rb[k].y : rb[k].x;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const T xa = ta[col][r0 + k * ROWS_PER_PASS];
+                if (comp)
+                    ra[k].y = xa;
+                else
+                    ra[k].x = xa;
+                if (!self) {
+                    const T xb = tb[col][r0 + k * ROWS_PER_PASS];
+                    if (comp)
+                        rb[k].y = xb;
+                    else
+                        rb[k].x = xb;
+                }
+            }
+            __syncthreads();
+        }
+        // ra[k] is element (col, a) of tile A: row a of B's place, and rb[k]
+        // row a of A's place (a = r0 + k * ROWS_PER_PASS)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int64_t a = r0 + k * ROWS_PER_PASS;
+            if (self) {
+                st(baseA + a * rowA + col, ra[k]);
+            } else {
+                st(baseB + a * rowA + col, ra[k]);
+                st(baseA + a * rowA + col, rb[k]);
+            }
+        }
+        return;
+    } else {
 #pragma unroll
     for (int a = r0; a < TS; a += ROWS_PER_PASS) ta[a][col] = ld(baseA + a * rowA + col);
     if (!self) {
@@ -64,6 +120,7 @@ __global__ void __launch_bounds__(NT) swap_kernel(SwapParams p)
             st(baseB + a * rowA + col, ta[col][a]);
             st(baseA + a * rowA + col, tb[col][a]);
         }
+    }
     }
 }
 
@@ -136,27 +193,42 @@ hipError_t launch_stage(int dtype_bytes, int layout, int logl, int lines, int se
     return hipErrorInvalidValue;
 }
 
+// The component-wise transpose of the swap, for complex64 with at least
+// EFFT_SWAP_SPLIT8_MIN_M middle slabs.  Measured on gfx950 (in place, swap
+// pass): 2^31 (M = 2^17) 9.24 -> 8.48 ms, 2^32 (2^16) 16.2 -> 15.1, 2^33
+// (2^19) 37.4 -> 34.7, 2^34 (2^16) 59.3 -> 54.3; slower at 2^30, M = 2^10
+// (3.56 -> 3.65) and 2^12 (3.06 -> 3.23); 2^28, M = 2^8, 0.95 -> 0.89.
+// Complex128 (two workgroups per CU instead of one) lost at 2^30: 6.03 ->
+// 7.20 ms.
+#ifndef EFFT_SWAP_SPLIT8_MIN_M
+#define EFFT_SWAP_SPLIT8_MIN_M (int64_t(1) << 13)
+#endif
+
 static hipError_t launch_swap_z(int dtype_bytes, const SwapParams &p, unsigned nz, hipStream_t stream)
 {
     const int64_t ts = p.R / p.nt;
     const dim3 grid(unsigned(p.M), unsigned(p.nt * p.nt), nz);
-#define EFFT_SWAP(T, TSV, NTV)                                                                      \
+#define EFFT_SWAP(T, TSV, NTV, SPL)                                                                 \
     if (ts == TSV) {                                                                                \
         if (g_dry_run) return hipSuccess;                                                           \
         if (p.nt_hint)                                                                              \
-            hipLaunchKernelGGL((swap_kernel<T, TSV, NTV, true>), grid, dim3(NTV), 0, stream, p);    \
+            hipLaunchKernelGGL((swap_kernel<T, TSV, NTV, true, SPL>), grid, dim3(NTV), 0, stream, p);  \
         else                                                                                        \
-            hipLaunchKernelGGL((swap_kernel<T, TSV, NTV, false>), grid, dim3(NTV), 0, stream, p);   \
+            hipLaunchKernelGGL((swap_kernel<T, TSV, NTV, false, SPL>), grid, dim3(NTV), 0, stream, p); \
         return hipGetLastError();                                                                   \
     }
     if (dtype_bytes == 16) {
-        EFFT_SWAP(double, 64, 512)
-        EFFT_SWAP(double, 32, 256)
-        EFFT_SWAP(double, 16, 256)
+        EFFT_SWAP(double, 64, 512, false)
+        EFFT_SWAP(double, 32, 256, false)
+        EFFT_SWAP(double, 16, 256, false)
+    } else if (dtype_bytes == 8 && p.M >= EFFT_SWAP_SPLIT8_MIN_M) {
+        EFFT_SWAP(float, 64, 512, true)
+        EFFT_SWAP(float, 32, 256, true)
+        EFFT_SWAP(float, 16, 256, true)
     } else if (dtype_bytes == 8) {
-        EFFT_SWAP(float, 64, 512)
-        EFFT_SWAP(float, 32, 256)
-        EFFT_SWAP(float, 16, 256)
+        EFFT_SWAP(float, 64, 512, false)
+        EFFT_SWAP(float, 32, 256, false)
+        EFFT_SWAP(float, 16, 256, false)
     }
 #undef EFFT_SWAP
     return hipErrorInvalidValue;
