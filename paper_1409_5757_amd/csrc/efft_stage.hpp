@@ -549,10 +549,17 @@ __device__ __forceinline__ void store_points(V *p, int64_t stride, const V *w, i
 #ifndef EFFT_SPLIT_R2C
 #define EFFT_SPLIT_R2C 1
 #endif
+// the same for the columns-to-rows pass (LAYOUT_COL2ROW, the out-of-place
+// first pass) of complex128 (measured on gfx950: 2^30 out of place, 8.57 ->
+// 7.24 ms; 2^28 2.21 -> 1.88 ms; 2^20 25 -> 21 us)
+#ifndef EFFT_SPLIT_C2R
+#define EFFT_SPLIT_C2R 1
+#endif
 template <typename V, int LOGL, int SETS, int LAYOUT> constexpr bool split_exchange()
 {
     if (Radices<LOGL>::NSTEPS < 2) return false;
     if (LAYOUT == LAYOUT_ROW2COL) return sizeof(decltype(V{}.x)) == 8 && EFFT_SPLIT_R2C && SETS == 1;
+    if (LAYOUT == LAYOUT_COL2ROW) return sizeof(decltype(V{}.x)) == 8 && EFFT_SPLIT_C2R && SETS == 1;
     const bool col = LAYOUT == LAYOUT_COL || LAYOUT == LAYOUT_COL_POST;
     if (!col && LAYOUT != LAYOUT_ROW) return false;
     const int mode = sizeof(decltype(V{}.x)) == 8 ? EFFT_SPLIT_C128 : EFFT_SPLIT_C64;
@@ -681,17 +688,47 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
     } else {
         // outputs land in LDS in natural order; re-read them one contiguous
         // row per line and write that row at its digit-reversed position
-        line_fft<V, LOGL, true, EP, TWL>(v[0], lds_line, t, sp.tt, sp.n_over_l, ltw);
-        __syncthreads();
         const int t2 = tid % P;
         const int c2 = tid / P;
+        constexpr bool SPLIT = LAYOUT == LAYOUT_COL2ROW && split_exchange<V, LOGL, SETS, LAYOUT>();
+        V w[E];
+        if constexpr (SPLIT) {
+            // through a buffer of real numbers, one component at a time (as
+            // in the rows-to-columns pass), into the same registers
+            using T = decltype(V{}.x);
+            T *lt = reinterpret_cast<T *>(lds);
+            line_fft<V, LOGL, false, EP, TWL, true>(v[0], reinterpret_cast<V *>(lt + c * PADDED), t, sp.tt,
+                                                    sp.n_over_l, ltw);
+#pragma unroll
+            for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+                for (int i = 0; i < E; ++i) lt[c * PADDED + lds_pad(t + P * i)] = comp ? v[0][i].y : v[0][i].x;
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    const T x = lt[c2 * PADDED + lds_pad(t2 + P * i)];
+                    if (comp)
+                        v[0][i].y = x;
+                    else
+                        v[0][i].x = x;
+                }
+                __syncthreads();
+            }
+        } else {
+            line_fft<V, LOGL, true, EP, TWL>(v[0], lds_line, t, sp.tt, sp.n_over_l, ltw);
+            __syncthreads();
+        }
         // one block per signal (B = N): line = signal * s + offset o2
         const int64_t line = a.tile * LINES + c2;
         const int64_t o2 = line & (sp.s - 1);
-        const V *row_lds = lds + c2 * PADDED;
-        V w[E];
+        if constexpr (SPLIT) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) w[i] = row_lds[lds_pad(t2 + P * i)];
+            for (int i = 0; i < E; ++i) w[i] = v[0][i];
+        } else {
+            const V *row_lds = lds + c2 * PADDED;
+#pragma unroll
+            for (int i = 0; i < E; ++i) w[i] = row_lds[lds_pad(t2 + P * i)];
+        }
         apply_stage_twiddle<V, E, P>(w, t2, uint64_t(o2), sp.tw_scale, sp.tt);
         finish_outputs<V, E>(w, sp);
         const int64_t row = (line - o2) * L + sp.row_mul * int64_t(digit_reverse(uint64_t(o2), sp.rev));
