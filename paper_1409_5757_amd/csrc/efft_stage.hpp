@@ -555,11 +555,17 @@ __device__ __forceinline__ void store_points(V *p, int64_t stride, const V *w, i
 #ifndef EFFT_SPLIT_C2R
 #define EFFT_SPLIT_C2R 1
 #endif
+// and for its form that applies factors as it loads (LAYOUT_COL2ROW_PRE, the
+// chirp path's first passes: 2^28 + 1 complex128 in place, 47.0 -> 43.7 ms)
+#ifndef EFFT_SPLIT_C2R_PRE
+#define EFFT_SPLIT_C2R_PRE 1
+#endif
 template <typename V, int LOGL, int SETS, int LAYOUT> constexpr bool split_exchange()
 {
     if (Radices<LOGL>::NSTEPS < 2) return false;
     if (LAYOUT == LAYOUT_ROW2COL) return sizeof(decltype(V{}.x)) == 8 && EFFT_SPLIT_R2C && SETS == 1;
     if (LAYOUT == LAYOUT_COL2ROW) return sizeof(decltype(V{}.x)) == 8 && EFFT_SPLIT_C2R && SETS == 1;
+    if (LAYOUT == LAYOUT_COL2ROW_PRE) return sizeof(decltype(V{}.x)) == 8 && EFFT_SPLIT_C2R_PRE && SETS == 1;
     const bool col = LAYOUT == LAYOUT_COL || LAYOUT == LAYOUT_COL_POST;
     if (!col && LAYOUT != LAYOUT_ROW) return false;
     const int mode = sizeof(decltype(V{}.x)) == 8 ? EFFT_SPLIT_C128 : EFFT_SPLIT_C64;
@@ -690,7 +696,7 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
         // row per line and write that row at its digit-reversed position
         const int t2 = tid % P;
         const int c2 = tid / P;
-        constexpr bool SPLIT = LAYOUT == LAYOUT_COL2ROW && split_exchange<V, LOGL, SETS, LAYOUT>();
+        constexpr bool SPLIT = split_exchange<V, LOGL, SETS, LAYOUT>();
         V w[E];
         if constexpr (SPLIT) {
             // through a buffer of real numbers, one component at a time (as
