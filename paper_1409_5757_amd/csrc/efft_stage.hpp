@@ -602,7 +602,10 @@ __device__ __forceinline__ void process_tile(V (&v)[SETS][E], const TileLines<SE
         if constexpr (SPLIT) {
             // outputs k = t + P*i stay in registers; the transpose goes
             // through a buffer of real numbers, the real parts first, each
-            // read overwriting only the component already written
+            // read overwriting only the component already written (written
+            // out here and in the columns-to-rows branch: as one shared
+            // helper the compiler gave these kernels 138-144 VGPRs instead of
+            // 127-128, one workgroup per CU instead of two)
             using T = decltype(V{}.x);
             T *lt = reinterpret_cast<T *>(lds);
             line_fft<V, LOGL, false, EP, TWL, true>(v[0], reinterpret_cast<V *>(lt + c * PADDED), t, sp.tt,
@@ -754,8 +757,21 @@ template <int LOGL, int LINES, int EP> constexpr int stage_threads()
     return LINES * LineGeom<(1 << LOGL), EP>::P;
 }
 
+// Waves per SIMD a pass kernel must leave room for: the component-wise
+// exchange exists so that two 512-thread workgroups share a CU (4 waves per
+// SIMD, at most 128 VGPRs each), and the bound keeps a code change from
+// silently taking that back.
+template <typename T, int LOGL, int LINES, int SETS, int LAYOUT, int EP> constexpr int stage_min_waves()
+{
+    return (split_exchange<typename vec2<T>::type, LOGL, SETS, LAYOUT>() &&
+            stage_threads<LOGL, LINES, EP>() == 512)
+               ? 4
+               : 1;
+}
+
 template <typename T, int LOGL, int LINES, int SETS, int LAYOUT, int PIPE, int EP>
-__global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()))
+__global__ void __launch_bounds__((stage_threads<LOGL, LINES, EP>()),
+                                  (stage_min_waves<T, LOGL, LINES, SETS, LAYOUT, EP>()))
     stage_kernel(StageParams sp)
 {
     using V = typename vec2<T>::type;
