@@ -326,9 +326,12 @@ inline int col_lines(int dtype_bytes, int logl, int64_t stride, bool same_positi
 #ifndef EFFT_C64_SETS8
 #define EFFT_C64_SETS8 1
 #endif
+#ifndef EFFT_SETS_MIN_STRIDE
+#define EFFT_SETS_MIN_STRIDE (int64_t(1) << 16)
+#endif
 inline int col_sets(int dtype_bytes, int logl, int lines, int64_t stride)
 {
-    if (lines != col_lines_max(dtype_bytes, logl) || stride < (int64_t(1) << 16)) return 1;
+    if (lines != col_lines_max(dtype_bytes, logl) || stride < EFFT_SETS_MIN_STRIDE) return 1;
     if (logl == 9 && dtype_bytes == 8) return EFFT_C64_SETS9 ? 2 : 1;
     if (logl == 8 && dtype_bytes == 8) return EFFT_C64_SETS8 ? 2 : 1;
     const int want = dtype_bytes == 16 ? EFFT_COL_SETS : EFFT_C64_COL_SETS;
