@@ -267,10 +267,18 @@ inline int col_order(int64_t stride) { return stride >= WIDE_TILE_STRIDE ? TILE_
 // 129 tiles (2^30 complex128 in place, first pass 8.03 -> 7.78 ms; 2^34
 // complex64, 81.3 -> 78.5 ms), while the transposing first pass of 2^32
 // complex64 (512-byte rows) lost 17% there and keeps 1031.
+// Strided passes with 512-byte tile rows (complex64 512-point lines in two
+// sets of 32) keep 1031: at 2^34 in place, first pass, 129 gave 76.6-76.8 ms
+// and 517 75.8 ms against 75.0-75.8 ms.
+#ifndef EFFT_SCATTER_512
+#define EFFT_SCATTER_512 1031
+#endif
 inline int64_t scatter_stride(int layout, int lines, int sets, int dtype_bytes)
 {
-    return ((layout == LAYOUT_COL || layout == LAYOUT_COL_POST) && lines * sets * dtype_bytes == 256) ? 129
-                                                                                                       : 1031;
+    const bool col = layout == LAYOUT_COL || layout == LAYOUT_COL_POST;
+    if (col && lines * sets * dtype_bytes == 256) return 129;
+    if (col && lines * sets * dtype_bytes == 512) return EFFT_SCATTER_512;
+    return 1031;
 }
 
 // Lines per workgroup for complex64 lines of 1024 points at a small stride:
