@@ -940,6 +940,12 @@ static hipError_t dispatch_logl(int layout, int lines, int sets, const StagePara
                 if (lines == C64_SHARED_LINES && sets == 1)
                     return launch_one<T, LOGL, C64_SHARED_LINES, 1, LAYOUT_COL, EPC>(p, stream);
             }
+            if constexpr (LOGL >= 8 && WMIN / 2 >= 2) {
+                if (lines == WMIN / 2 && sets == 1) return launch_one<T, LOGL, WMIN / 2, 1, LAYOUT_COL, EPC>(p, stream);
+            }
+            if constexpr (LOGL >= 8 && WMIN / 4 >= 2) {
+                if (lines == WMIN / 4 && sets == 1) return launch_one<T, LOGL, WMIN / 4, 1, LAYOUT_COL, EPC>(p, stream);
+            }
         }
         if (layout == LAYOUT_COL_POST) {
             if (lines == WMAX && sets == 1) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL_POST, EPC>(p, stream);
@@ -964,6 +970,13 @@ static hipError_t dispatch_logl(int layout, int lines, int sets, const StagePara
             if (lines == WMAX) return launch_one<T, LOGL, WMAX, 1, LAYOUT_COL2ROW, EPC>(p, stream);
             if constexpr (WMIN != WMAX) {
                 if (lines == WMIN) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL2ROW, EPC>(p, stream);
+            }
+            // narrower tiles for grids too small to fill the device
+            if constexpr (LOGL >= 8 && WMIN / 2 >= 2) {
+                if (lines == WMIN / 2) return launch_one<T, LOGL, WMIN / 2, 1, LAYOUT_COL2ROW, EPC>(p, stream);
+            }
+            if constexpr (LOGL >= 8 && WMIN / 4 >= 2) {
+                if (lines == WMIN / 4) return launch_one<T, LOGL, WMIN / 4, 1, LAYOUT_COL2ROW, EPC>(p, stream);
             }
         }
         if (layout == LAYOUT_ROW2COL && sets == 1) {
