@@ -266,6 +266,24 @@ void narrow_small_grids(const efft_plan_s *p, std::vector<Pass> &v)
     }
 }
 
+// A pass copied from plan `p` whose layout was changed afterwards (the chirp
+// path's fused first and last passes) may have been narrowed for a layout
+// with more tile widths: double its lines until a kernel for the new layout
+// exists.  False if none does.
+bool widen_to_kernel(const efft_plan_s *p, Pass &ps)
+{
+    for (;;) {
+        set_dry_run(true);
+        const hipError_t e = launch_stage(p->eb, ps.layout, ps.logl, ps.lines, ps.sets, ps.sp, nullptr);
+        set_dry_run(false);
+        if (e == hipSuccess) return true;
+        const int64_t nt = tiles_for(p, ps, ps.lines * 2, ps.sets);
+        if (nt < 0) return false;
+        ps.lines *= 2;
+        ps.sp.ntiles = nt;
+    }
+}
+
 void build_passes(efft_plan_s *p, const TwTable &tt)
 {
     build_passes_unscaled(p, tt);
@@ -945,6 +963,13 @@ efft_plan_s *create_chirp(int64_t n, int64_t batch, int dtype, int dir, int inpl
             last.sp.post = p->chirp;
             last.sp.post_scale = p->scale;
             last.sp.n_valid = n;
+        }
+        if (!widen_to_kernel(p->inner, p->chirp_fwd.front()) || !widen_to_kernel(p->inner2, p->chirp_bwd.front()) ||
+            (p->chirp_post && !widen_to_kernel(p->inner2, p->chirp_bwd.back()))) {
+            // no fused kernel for these tiles: separate pre- and post-multiply passes
+            p->chirp_fwd.clear();
+            p->chirp_bwd.clear();
+            p->chirp_post = false;
         }
     }
     // V = DFT_M(v) / M, formed in the work array and transformed into vhat
