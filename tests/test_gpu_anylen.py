@@ -1,6 +1,7 @@
 """Lengths that are not powers of two (the chirp path): every bin against the
 oracle's direct sum of Eq. "eqf" up to N ~ 10^4, sampled bins against it at
-larger N, closed-form tones, round trips, batches, and argument handling.
+larger N, closed-form tones, round trips, batches, prime lengths whose
+M-point plans have narrowed strided passes, and argument handling.
 Tolerances are the path's bars (FP64 rel-L2 <= 1e-12, FP32 <= 1e-5); for
 sampled bins the error of each bin is taken relative to the RMS of the
 spectrum, which equals ||x||_2 (Parseval)."""
@@ -77,6 +78,30 @@ def test_round_trip_and_batch(dtype):
         api.fft(w, inplace=True)
         assert torch.equal(w, y)
         torch.cuda.synchronize()
+
+
+# Prime lengths whose M-point plans (M = 2^15 .. 2^20, two strided passes)
+# have fewer tiles than the device has CUs: the planner narrows those passes,
+# and the chirp plan's fused first pass (pre-multiply as it loads) and last
+# pass (post-multiply as it stores) must still run with tiles that have a
+# kernel for their own layout.
+CHIRP_SMALL_M = [9973, 25013, 50021, 100003, 300007]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", CHIRP_SMALL_M)
+def test_chirp_fused_passes_on_small_m_point_plans(dtype, n):
+    for direction, inplace in ((-1, True), (1, False)):
+        x = host_input("uniform", 4000 + n, n, dtype)
+        got, after = run_library(x, dtype, direction, inplace)
+        bins = sample_bins(n, 24, seed=n % 977)
+        ref = oracle.dft_at(x, bins, sign=direction)
+        err = rel_l2(got[bins], ref)
+        print(f"n={n} {dtype} dir={direction} inplace={inplace}: rel_l2 over {len(bins)} bins = {err:.2e}",
+              flush=True)
+        assert err <= TOL[dtype], (n, direction, inplace, err)
+        if after is not None:
+            np.testing.assert_array_equal(after, x)
 
 
 def test_plan_reports_memory_and_passes():
