@@ -13,9 +13,13 @@ namespace efft {
 // ------------------------------------------------------------------- swap
 // Workgroup (I, J, mu) exchanges tile A = rows I*TS.., cols J*TS.. of slab mu
 // with tile B = rows J*TS.., cols I*TS.. of slab rev(mu), each transposed.
-// Each unordered pair is handled by the workgroup whose key is the smaller;
-// a tile paired with itself is transposed in place.  Every element is read
-// and written exactly once.
+// The grid holds only the tile pairs with I <= J (the pair (J, I, rev(mu))
+// is the same exchange); on the diagonal I == J the slabs mu and rev(mu) pair
+// up and the workgroup with the smaller of the two takes them, and a tile
+// paired with itself is transposed in place.  Every element is read and
+// written exactly once.  (A grid over every (I, J) whose second workgroup of
+// each pair returns at once launched about twice the workgroups, each
+// holding the LDS of a CU while it starts and exits.)
 //
 // SPLIT: both tiles are loaded into registers and transposed through LDS one
 // component at a time (real parts, then imaginary parts; each read overwrites
@@ -30,16 +34,18 @@ __global__ void __launch_bounds__(NT) swap_kernel(SwapParams p)
     __shared__ E ta[TS][TS + 1];
     __shared__ E tb[TS][TS + 1];
 
-    // grid: x = middle index mu (up to 2^24), y = tile pair I*nt + J (up to 1024)
+    // grid: x = middle index mu (up to 2^24), y = tile pair I <= J numbered
+    // row by row (nt * (nt + 1) / 2 of them; row I holds J = I .. nt - 1)
     const int64_t mu = order_tiles(blockIdx.x, p.M, TILE_XCD);
-    const int64_t ij = blockIdx.y;
-    const int64_t I = ij / p.nt;
-    const int64_t J = ij - I * p.nt;
+    int64_t I = 0, rem = blockIdx.y;
+    while (rem >= p.nt - I) {
+        rem -= p.nt - I;
+        ++I;
+    }
+    const int64_t J = I + rem;
     const int64_t rmu = int64_t(digit_reverse(uint64_t(mu), p.mid));
-    const int64_t key = ij * p.M + mu;
-    const int64_t pkey = (J * p.nt + I) * p.M + rmu;
-    if (key > pkey) return;
-    const bool self = (key == pkey);
+    if (I == J && mu > rmu) return;  // taken by the workgroup of slab rmu
+    const bool self = I == J && mu == rmu;
 
     V *x = static_cast<V *>(p.data) + int64_t(blockIdx.z) * p.n;  // signal of a batch
     const int col = threadIdx.x % TS;
@@ -207,7 +213,7 @@ hipError_t launch_stage(int dtype_bytes, int layout, int logl, int lines, int se
 static hipError_t launch_swap_z(int dtype_bytes, const SwapParams &p, unsigned nz, hipStream_t stream)
 {
     const int64_t ts = p.R / p.nt;
-    const dim3 grid(unsigned(p.M), unsigned(p.nt * p.nt), nz);
+    const dim3 grid(unsigned(p.M), unsigned(p.nt * (p.nt + 1) / 2), nz);
 #define EFFT_SWAP(T, TSV, NTV, SPL)                                                                 \
     if (ts == TSV) {                                                                                \
         if (g_dry_run) return hipSuccess;                                                           \
@@ -236,7 +242,7 @@ static hipError_t launch_swap_z(int dtype_bytes, const SwapParams &p, unsigned n
 
 hipError_t launch_swap(int dtype_bytes, const SwapParams &p, int64_t batch, hipStream_t stream)
 {
-    if (p.M > (int64_t(1) << 24) || p.nt * p.nt > 65535) return hipErrorInvalidValue;
+    if (p.M > (int64_t(1) << 24) || p.nt < 1 || p.nt * (p.nt + 1) / 2 > 65535) return hipErrorInvalidValue;
     // signals of a batch along grid z, at most 65535 per launch
     for (int64_t b0 = 0; b0 < batch; b0 += 65535) {
         SwapParams q = p;
