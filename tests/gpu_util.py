@@ -76,3 +76,22 @@ def device_rel_l2(a: torch.Tensor, b: torch.Tensor, chunk: int = 1 << 26) -> flo
         den += float(torch.sum(bb.real ** 2 + bb.imag ** 2))
         del d, bb
     return (num / den) ** 0.5 if den > 0 else num ** 0.5
+
+
+def tone_spectrum_errors(y, seed: int, n: int):
+    """Error of the forward transform ``y`` (on the device) of
+    ``inputs.fill_tones_torch(seed)`` against its exact spectrum on every bin
+    (N e^{i phi} at the 8 tone bins, zero elsewhere): (relative L2 over all N
+    bins, largest absolute error / N, largest tone-bin error / N).  N is the
+    largest |F_k|.  The tone bins of ``y`` are zeroed."""
+    f, v = inputs.tone_spectrum_peaks(seed, n)
+    fi = torch.from_numpy(f).to(y.device)
+    perr = np.abs(y[fi].cpu().numpy().astype(np.complex128) - v)
+    y[fi] = 0
+    off_sq, off_max = 0.0, 0.0
+    for i in range(0, n, 1 << 26):
+        a = y[i:i + (1 << 26)].abs().double()
+        off_sq += float(torch.sum(a * a))
+        off_max = max(off_max, float(a.max()))
+    rel = ((off_sq + float(np.sum(perr ** 2))) / float(np.sum(np.abs(v) ** 2))) ** 0.5
+    return rel, max(off_max, float(perr.max())) / n, float(perr.max()) / n
