@@ -346,6 +346,22 @@ inline int col_sets(int dtype_bytes, int logl, int lines, int64_t stride)
     return (want >= 2 && logl == 10 && lines * dtype_bytes == 128) ? 2 : 1;
 }
 
+// Lines per set of a two-set tile of complex64 lines of 256 points: half the
+// widest tile (two sets of 32 lines, 512-byte runs, 512 threads) so that the
+// LDS holds two workgroups per CU, instead of two sets of 64 (1 KiB runs,
+// 1024 threads, one workgroup per CU).  Measured on gfx950 (bitwise the same
+// output): 2^34 complex64 in place, second pass (stride 2^17) 50.3 -> 47.6
+// ms; 2^32 out of place, strided passes 13.93 -> 13.57 and 14.96 -> 14.63
+// ms.  Half-width tiles of 512-point lines (two sets of 16, 256-byte runs)
+// lost at the 2^25 stride of the 2^34 first pass (75.7 -> 106 ms).
+#ifndef EFFT_C64_HALF_SETS8
+#define EFFT_C64_HALF_SETS8 1
+#endif
+inline int col_set_lines(int dtype_bytes, int logl, int lines, int sets)
+{
+    return (EFFT_C64_HALF_SETS8 && dtype_bytes == 8 && logl == 8 && sets == 2) ? lines / 2 : lines;
+}
+
 // Non-temporal hints of a pass (measured on gfx950 at 2^30 points: they speed
 // up the large-stride column passes by about 10%, the row passes by about 5%,
 // and the stores of every pass; only the loads of small-stride column passes,
