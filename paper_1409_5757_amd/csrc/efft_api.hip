@@ -378,7 +378,7 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
                 ps.layout = LAYOUT_COL;
                 ps.lines = col_lines(p->eb, d[j], s, true, true);
                 ps.sets = col_sets(p->eb, d[j], ps.lines, s);
-                ps.lines = col_set_lines(p->eb, d[j], ps.lines, ps.sets);
+                ps.lines = col_set_lines(p->eb, d[j], ps.lines, ps.sets, s);
                 ps.sp.order = col_order(s);
                 ps.sp.twmode = TW_OFFSET;
                 ps.sp.tw_scale = uint64_t(n / (s * L));
@@ -447,7 +447,7 @@ void build_passes_unscaled(efft_plan_s *p, const TwTable &tt)
         ps.layout = LAYOUT_COL;
         ps.lines = col_lines(p->eb, d[j], C, true, true);
         ps.sets = col_sets(p->eb, d[j], ps.lines, C);
-        ps.lines = col_set_lines(p->eb, d[j], ps.lines, ps.sets);
+        ps.lines = col_set_lines(p->eb, d[j], ps.lines, ps.sets, C);
         const int64_t L = int64_t(1) << d[j];
         ps.sp = base_params(p, tt);
         ps.sp.order = col_order(C);

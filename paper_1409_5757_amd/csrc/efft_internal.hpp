@@ -346,20 +346,29 @@ inline int col_sets(int dtype_bytes, int logl, int lines, int64_t stride)
     return (want >= 2 && logl == 10 && lines * dtype_bytes == 128) ? 2 : 1;
 }
 
-// Lines per set of a two-set tile of complex64 lines of 256 points: half the
-// widest tile (two sets of 32 lines, 512-byte runs, 512 threads) so that the
-// LDS holds two workgroups per CU, instead of two sets of 64 (1 KiB runs,
-// 1024 threads, one workgroup per CU).  Measured on gfx950 (bitwise the same
-// output): 2^34 complex64 in place, second pass (stride 2^17) 50.3 -> 47.6
-// ms; 2^32 out of place, strided passes 13.93 -> 13.57 and 14.96 -> 14.63
-// ms.  Half-width tiles of 512-point lines (two sets of 16, 256-byte runs)
-// lost at the 2^25 stride of the 2^34 first pass (75.7 -> 106 ms).
+// Lines per set of the widest strided tile of complex64 lines of 256 points
+// (64 lines, 1024 threads, one workgroup per CU): half of them (512 threads)
+// so that the LDS holds two workgroups per CU, for two-set tiles and for
+// one-set tiles at strides from EFFT_C64_HALF_ONE_MIN_STRIDE.  Measured on
+// gfx950 (bitwise the same output): two sets, 2^34 complex64 in place second
+// pass (stride 2^17) 50.3 -> 47.6 ms, 2^32 out of place strided passes 13.93
+// -> 13.57 and 14.96 -> 14.63 ms; one set, the 2^34 third pass (stride 2^9)
+// 49.35 -> 47.12 ms, but the 2^32 out-of-place second pass (stride 2^8)
+// 12.15 -> 12.51 ms.  Half-width tiles of 512-point lines (two sets of 16,
+// 256-byte runs) lost at the 2^25 stride of the 2^34 first pass (75.7 -> 106
+// ms), and a half-width transposing first pass gained nothing (2^32, 15.81 ->
+// 15.76 ms).
 #ifndef EFFT_C64_HALF_SETS8
 #define EFFT_C64_HALF_SETS8 1
 #endif
-inline int col_set_lines(int dtype_bytes, int logl, int lines, int sets)
+#ifndef EFFT_C64_HALF_ONE_MIN_STRIDE
+#define EFFT_C64_HALF_ONE_MIN_STRIDE (int64_t(1) << 9)
+#endif
+inline int col_set_lines(int dtype_bytes, int logl, int lines, int sets, int64_t stride)
 {
-    return (EFFT_C64_HALF_SETS8 && dtype_bytes == 8 && logl == 8 && sets == 2) ? lines / 2 : lines;
+    if (dtype_bytes != 8 || logl != 8 || lines != col_lines_max(dtype_bytes, logl)) return lines;
+    if (sets == 2) return EFFT_C64_HALF_SETS8 ? lines / 2 : lines;
+    return stride >= EFFT_C64_HALF_ONE_MIN_STRIDE ? lines / 2 : lines;
 }
 
 // Non-temporal hints of a pass (measured on gfx950 at 2^30 points: they speed

@@ -758,12 +758,14 @@ template <int LOGL, int LINES, int EP> constexpr int stage_threads()
 }
 
 // Waves per SIMD a pass kernel must leave room for: the component-wise
-// exchange, and the two-set complex64 tile of 512 threads, exist so that two
-// 512-thread workgroups share a CU (4 waves per SIMD, at most 128 VGPRs
-// each), and the bound keeps a code change from silently taking that back.
+// exchange, and the half-width complex64 tiles of 256-point lines, exist so
+// that two 512-thread workgroups share a CU (4 waves per SIMD, at most 128
+// VGPRs each), and the bound keeps a code change from silently taking that
+// back.
 template <typename T, int LOGL, int LINES, int SETS, int LAYOUT, int EP> constexpr int stage_min_waves()
 {
-    return ((split_exchange<typename vec2<T>::type, LOGL, SETS, LAYOUT>() || (sizeof(T) == 4 && SETS == 2)) &&
+    return ((split_exchange<typename vec2<T>::type, LOGL, SETS, LAYOUT>() ||
+             (sizeof(T) == 4 && LOGL == 8 && LAYOUT == LAYOUT_COL)) &&
             stage_threads<LOGL, LINES, EP>() == 512)
                ? 4
                : 1;
@@ -935,6 +937,9 @@ static hipError_t dispatch_logl(int layout, int lines, int sets, const StagePara
             }
             if constexpr (LOGL == 8 && EB == 8) {  // the half-width two-set tile (col_set_lines)
                 if (lines == WMAX / 2 && sets == 2) return launch_one<T, LOGL, WMAX / 2, 2, LAYOUT_COL, EPC>(p, stream);
+            }
+            if constexpr (LOGL == 8 && EB == 8) {  // the half-width one-set tile (col_set_lines)
+                if (lines == WMAX / 2 && sets == 1) return launch_one<T, LOGL, WMAX / 2, 1, LAYOUT_COL, EPC>(p, stream);
             }
             if constexpr (WMIN != WMAX) {
                 if (lines == WMIN && sets == 1) return launch_one<T, LOGL, WMIN, 1, LAYOUT_COL, EPC>(p, stream);
