@@ -327,10 +327,11 @@ inline int col_lines(int dtype_bytes, int logl, int64_t stride, bool same_positi
 #ifndef EFFT_C64_SETS9
 #define EFFT_C64_SETS9 1
 #endif
-// Complex64 lines of 256 points: two sets of 64 lines (1 KiB runs) at large
-// strides (1), or one set of 64 (0).  Measured on gfx950: the last pass of
-// 2^32 out of place (stride 2^24) 16.2 -> 15.0 ms, the second pass of 2^34
-// in place (stride 2^17) 51.0 -> 49.2 ms.
+// Complex64 lines of 256 points: two line sets at large strides (1), or one
+// (0); col_set_lines below sets the lines per set.  Measured on gfx950 with
+// sets of 64 lines (1 KiB runs): the last pass of 2^32 out of place (stride
+// 2^24) 16.2 -> 15.0 ms, the second pass of 2^34 in place (stride 2^17) 51.0
+// -> 49.2 ms.
 #ifndef EFFT_C64_SETS8
 #define EFFT_C64_SETS8 1
 #endif

@@ -19,8 +19,9 @@ Which plan shape each size reaches (digits log2, planner's choice):
   stride (the 2^30 complex64 first pass).
 * 2^26 complex64 in place, (9, 8, 9): 32 lines of 512 points at a 2^17
   stride (the 2^34 first pass).
-* 2^25 complex64 out of place, (9, 8, 8): two sets of 64 lines of 256 points
-  at a 2^17 stride (the last 2^32 out-of-place pass, and the 2^34 second
+* 2^25 complex64 out of place, (9, 8, 8): two sets of 32 lines of 256 points
+  at a 2^17 stride, 512 threads (the last 2^32 out-of-place pass, and the
+  2^34 second pass), after one set of 32 at a 2^9 stride (the 2^34 third
   pass).
 * 2^25 complex128 out of place, (9, 8, 8): the transposing first pass of
   512-point lines, two tiles per workgroup with the second tile's loads in
