@@ -1,6 +1,8 @@
 """Tuning: launch options never change the arithmetic (bit-identical results
-for every option the tuner tries), tuned decompositions stay within the
-oracle tolerance, and wisdom entries round-trip through a file."""
+for every option the tuner tries, among them the narrowed tiles of small
+grids at 2^20 and the one- and two-set tiles of 256-point complex64 lines at
+2^25), tuned decompositions stay within the oracle tolerance, and wisdom
+entries round-trip through a file."""
 import os
 import tempfile
 
@@ -16,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("q,dtype,inplace", [(20, torch.complex128, True), (22, torch.complex64, False),
-                                             (14, torch.complex128, False)])
+                                             (14, torch.complex128, False), (25, torch.complex64, False)])
 def test_every_option_gives_identical_bits(q, dtype, inplace):
     n = 1 << q
     xh = host_input("uniform", 40 + q, n, dtype)
