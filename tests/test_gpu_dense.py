@@ -24,9 +24,11 @@ Which plan shape each size reaches (digits log2, planner's choice):
   2^34 second pass), after one set of 32 at a 2^9 stride (the 2^34 third
   pass).
 * 2^25 complex128 out of place, (9, 8, 8): the transposing first pass of
-  512-point lines, two tiles per workgroup with the second tile's loads in
-  flight while the first is transformed, and the stride-2^8 middle pass of
-  single-set tiles with the component-wise LDS exchange.
+  512-point lines and the stride-2^8 middle pass, both single-set tiles with
+  the component-wise LDS exchange (two workgroups per CU; the transposing
+  kernel of 512-point lines spills two registers under that bound).  An
+  earlier form of that first pass ran two tiles per workgroup with the second
+  tile's loads in flight; the run-twice check below was added for it.
 
 Every plan above, and the out-of-place 2^26 and 2^27 complex128 plans, must
 also give bitwise the same output when run twice on the same input: a result
