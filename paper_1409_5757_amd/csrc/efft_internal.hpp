@@ -299,11 +299,22 @@ constexpr int C64_SHARED_LINES = 8;
 #define EFFT_C64_WIDE_SHORT 1
 #endif
 
+// Complex128 lines of 512 points written as rows (the transposing first pass
+// of out-of-place plans whose first digit is 2^9): 16 lines (256-byte runs)
+// from a 2^17-element stride, 8 below.  Measured on gfx950 (bitwise the same
+// output): 2^26 out of place 0.474 -> 0.435 ms, 2^27 0.912 -> 0.846 ms, but
+// 2^25 (stride 2^16) 0.215 -> 0.224 ms.
+#ifndef EFFT_C128_WIDE_ROWS9
+#define EFFT_C128_WIDE_ROWS9 1
+#endif
+
 inline int col_lines(int dtype_bytes, int logl, int64_t stride, bool same_positions, bool column_pass = false)
 {
     const int w = col_lines_max(dtype_bytes, logl);
     if (EFFT_C64_WIDE_SHORT && dtype_bytes == 8 && (logl == 8 || logl == 9) && stride >= w) return w;
     if (same_positions && stride >= WIDE_TILE_STRIDE && stride >= w) return w;
+    if (EFFT_C128_WIDE_ROWS9 && !same_positions && dtype_bytes == 16 && logl == 9 && stride >= WIDE_TILE_STRIDE)
+        return w;
     if (column_pass && dtype_bytes == 8 && logl == 10 && stride >= C64_SHARED_LINES) return C64_SHARED_LINES;
     return col_lines_narrow(dtype_bytes, logl);
 }
